@@ -1,0 +1,156 @@
+"""Oracle sample weights (FP64): tFFR, plain FFR and trapezoid quadrature.
+
+Test infrastructure only (see the package docstring).
+
+Readings taken where the paper's matrices do not conform or are under-specified:
+
+* The product that is inverted is the sample-indexed one, G = Psi W (P x P per azimuth
+  slice), so that W D f_hat in Algorithm 1 conforms and "diagonal" / "band" refer to
+  the sample index within the slice.  The inner-product order is the one under which
+  the untruncated product is the frame Gram matrix (unit diagonal).
+* W and Psi are both truncated to grid points m with |m - lam| < q (the bound of
+  Eq. (4)); q is not given for the frame methods, the default is q = 3.
+* The weight lattice is the image's own DFT lattice: the integers in cycles per field of
+  view, infinite and periodic.
+* tFFR keeps only the diagonal of G (Sec. III-C, "isolating the diagonal"):
+  D = diag(pinv(diag(G))), i.e. 1/g elementwise with 1/0 -> 0, then R_tau.
+* R_tau(x) = x if x >= tau else 0 (Sec. III-B), inclusive, compared on |x| (x is real
+  and positive here).  Mode 0 thresholds the entries of the pseudo-inverse as written;
+  mode 1 thresholds the correlation g itself ("preserving only the most correlated
+  values").
+* Plain FFR: D = B_r(pinv(G)) with r = 2 (Eq. (8) and Sec. IV, Baselines); B_r keeps
+  entries with |p - p'| <= r.
+* Quadrature: trapezoid rule per azimuth slice in lam (Sec. II-B and Sec. IV), half
+  intervals at both ends; azimuth is uniform so it carries no factor.
+"""
+
+import numpy as np
+
+from .window import r_psi, r_w
+
+THRESH_LITERAL = 0  # keep iff |1/g| >= tau
+THRESH_CORRELATION = 1  # keep iff g >= tau
+
+
+def grid_points(lam, q):
+    """Integers m with |m - lam| < q, as an array [..., K] plus a validity mask.
+
+    This is the truncation "only lambda_n within a chosen bound q are considered for
+    each l_m" of Eq. (4).
+    """
+    lam = np.asarray(lam, dtype=np.float64)
+    kmax = int(np.ceil(q)) + 1
+    base = np.floor(lam)[..., None]
+    offs = np.arange(-kmax, kmax + 1, dtype=np.float64)
+    m = base + offs
+    mask = np.abs(m - lam[..., None]) < q
+    return m, mask
+
+
+def frame_diagonal(lam, a=0.01, q=3.0):
+    """g = (Psi W)_{pp} = sum_{|m - lam| < q} R_Psi(m - lam) R_W(m - lam).
+
+    The diagonal of the (truncated) frame product for every sample (Sec. III-C, end:
+    only the diagonal of W Psi is needed for stripmap tFFR).
+    """
+    m, mask = grid_points(lam, q)
+    d = m - np.asarray(lam, dtype=np.float64)[..., None]
+    terms = r_psi(d, a) * r_w(d, a)
+    return np.sum(np.where(mask, terms, 0.0), axis=-1)
+
+
+def tffr_weights(lam, a=0.01, q=3.0, tau=0.97, mode=THRESH_LITERAL):
+    """tFFR weights D = R_tau(pinv(diag(Psi W))) for every sample (Sec. III-B/III-C).
+
+    Returns (d, kept) with d the weight (0 where thresholded) and kept the boolean mask
+    of surviving samples; kept.sum() is the count c of Sec. III-C.
+    """
+    g = frame_diagonal(lam, a, q)
+    with np.errstate(divide="ignore"):
+        inv = np.where(g != 0.0, 1.0 / g, 0.0)
+    if mode == THRESH_LITERAL:
+        kept = np.abs(inv) >= tau
+    elif mode == THRESH_CORRELATION:
+        kept = g >= tau
+    else:
+        raise ValueError("unknown threshold mode")
+    return np.where(kept, inv, 0.0), kept
+
+
+def quad_weights(lam):
+    """Trapezoid quadrature weights along each azimuth slice (Sec. II-B, Sec. IV).
+
+    alpha_p = (lam_{p+1} - lam_{p-1}) / 2 inside, (lam_1 - lam_0)/2 and
+    (lam_{P-1} - lam_{P-2})/2 at the ends; a single sample gets weight 1.
+    """
+    lam = np.atleast_2d(np.asarray(lam, dtype=np.float64))
+    n_rows, n_p = lam.shape
+    out = np.empty_like(lam)
+    if n_p == 1:
+        out[:] = 1.0
+        return out
+    for p in range(n_p):
+        lo = lam[:, max(p - 1, 0)]
+        hi = lam[:, min(p + 1, n_p - 1)]
+        out[:, p] = (hi - lo) / 2.0
+    return out
+
+
+def frame_product_row(lam_row, a=0.01, q=3.0):
+    """Truncated frame product G~ (P x P) for one azimuth slice.
+
+    G~_{pp'} = sum over integers m with |m - lam_p| < q and |m - lam_p'| < q of
+    R_Psi(m - lam_p) R_W(m - lam_p')  (Psi truncated around lam_p, W around lam_p').
+    """
+    lam_row = np.asarray(lam_row, dtype=np.float64)
+    n_p = lam_row.size
+    G = np.zeros((n_p, n_p))
+    for p in range(n_p):
+        m, mask = grid_points(lam_row[p], q)
+        m = m[mask]
+        for pp in range(n_p):
+            ok = np.abs(m - lam_row[pp]) < q
+            if not np.any(ok):
+                continue
+            mm = m[ok]
+            G[p, pp] = np.sum(r_psi(mm - lam_row[p], a) * r_w(mm - lam_row[pp], a))
+    return G
+
+
+def ffr_weights_row(lam_row, a=0.01, q=3.0, r=2):
+    """Plain FFR weights for one slice: D = B_r(pinv(G~)) (Eq. (8))."""
+    G = frame_product_row(lam_row, a, q)
+    Z = np.linalg.pinv(G)
+    n_p = lam_row.size
+    idx = np.arange(n_p)
+    band = np.abs(idx[:, None] - idx[None, :]) <= r
+    return np.where(band, Z, 0.0)
+
+
+def ffr_weights(lam, a=0.01, q=3.0, r=2):
+    """Plain FFR banded weights for every slice, stored as [n_pulses][n_freq][2r+1].
+
+    Entry [n, p, r + o] is D^{(n)}_{p, p+o} for o in [-r, r] (0 outside the row).
+    """
+    lam = np.atleast_2d(np.asarray(lam, dtype=np.float64))
+    n_rows, n_p = lam.shape
+    out = np.zeros((n_rows, n_p, 2 * r + 1))
+    for n in range(n_rows):
+        D = ffr_weights_row(lam[n], a, q, r)
+        for o in range(-r, r + 1):
+            for p in range(n_p):
+                if 0 <= p + o < n_p:
+                    out[n, p, r + o] = D[p, p + o]
+    return out
+
+
+def band_to_dense(band_row):
+    """[P][2r+1] band storage of one slice -> dense P x P matrix."""
+    n_p, width = band_row.shape
+    r = (width - 1) // 2
+    D = np.zeros((n_p, n_p))
+    for p in range(n_p):
+        for o in range(-r, r + 1):
+            if 0 <= p + o < n_p:
+                D[p, p + o] = band_row[p, r + o]
+    return D

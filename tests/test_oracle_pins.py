@@ -1,0 +1,475 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each check is a function of the oracle modules so that the mutation tests at the end
+can plant a plausible mistake (a dropped term, a flipped sign, a transposed operand)
+and show that some pin catches it.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate, optimize
+
+import oracle
+from oracle import entropy, geometry, nudft, pipeline, weights, window
+from paper_1910_10908_amd import scenes
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+def _tiny_problem(n_pulses=8, n_freq=16, m=16, fov=40.0, weighting=pipeline.WEIGHT_TFFR, **kw):
+    k, ku = scenes.radar_sampling(n_pulses, n_freq)
+    return pipeline.Problem(k=k, ku=ku, mx=m, my=m, fov_x=fov, fov_y=fov, weighting=weighting, **kw)
+
+
+# ---------------------------------------------------------------- K1: DFT special case
+def check_dft_lattice(nud=nudft):
+    """Samples exactly on the image's DFT lattice with unit weights: the sum is the inverse
+    2-D DFT (numpy.fft) times M^2, re-indexed to centred bins."""
+    M, L = 16, 40.0
+    rng = np.random.default_rng(1)
+    ix = np.arange(-M // 2, M // 2)
+    kx_row = 2 * np.pi * ix / L
+    kx = np.tile(kx_row, (M, 1))  # row n = azimuth bin, p = range bin
+    ky = 2 * np.pi * ix / L
+    c = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))
+    X = geometry.pixel_coordinates(M, L)
+    Y = geometry.pixel_coordinates(M, L)
+    got = nud.forward_direct(c, kx, ky, X, Y)
+    # numpy: F[a, b] = (1/M^2) sum_{u,v} C[u, v] exp(2 pi i (u a + v b)/M), u: range bin
+    Cfull = np.zeros((M, M), complex)
+    for n in range(M):
+        for p in range(M):
+            Cfull[ix[p] % M, ix[n] % M] = c[n, p]
+    F = np.fft.ifft2(Cfull) * M * M
+    jj = np.arange(M) - M // 2
+    ref = F[np.ix_(jj % M, jj % M)]
+    # pixel jx sits at X = (jx - M/2) L / M, i.e. DFT index jx - M/2
+    return _rel(got, ref)
+
+
+def test_k1_dft_lattice():
+    assert check_dft_lattice() < 1e-12
+
+
+# ---------------------------------------------------------------- K2: Dirichlet closed form
+def dirichlet_image(a, x0, y0, kx0, dkx, P, ky0, dky, N, X, Y):
+    def D(k0, dk, n, t):
+        t = np.asarray(t, float)
+        num = np.sin(n * dk * t / 2.0)
+        den = np.sin(dk * t / 2.0)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            core = np.where(np.abs(den) < 1e-300, n, num / den)
+        return np.exp(1j * (k0 + (n - 1) * dk / 2.0) * t) * core
+
+    return a * np.outer(D(kx0, dkx, P, X - x0), D(ky0, dky, N, Y - y0))
+
+
+def check_dirichlet(nud=nudft, form="direct"):
+    P, N, M, L = 24, 12, 32, 30.0
+    kx0, dkx, ky0, dky = 400.0, 0.37, -3.1, 0.29
+    kx = np.tile(kx0 + dkx * np.arange(P), (N, 1))
+    ky = ky0 + dky * np.arange(N)
+    a, x0, y0 = 0.7 - 0.4j, 3.3, -5.1
+    s = a * np.exp(-1j * (kx * x0 + ky[:, None] * y0))
+    X = geometry.pixel_coordinates(M, L)
+    Y = geometry.pixel_coordinates(M, L)
+    f = nud.forward_direct if form == "direct" else nud.forward_separable
+    got = f(s, kx, ky, X, Y)
+    ref = dirichlet_image(a, x0, y0, kx0, dkx, P, ky0, dky, N, X, Y)
+    return _rel(got, ref)
+
+
+@pytest.mark.parametrize("form", ["direct", "separable"])
+def test_k2_point_scatterer_dirichlet(form):
+    assert check_dirichlet(form=form) < 1e-12
+
+
+# ---------------------------------------------------------------- K3: adjoint identity
+def check_adjoint(nud=nudft):
+    rng = np.random.default_rng(3)
+    prob = _tiny_problem(6, 10, 12)
+    kx, ky, lam, X, Y = prob.geometry()
+    x = rng.standard_normal(kx.shape) + 1j * rng.standard_normal(kx.shape)
+    y = rng.standard_normal((12, 12)) + 1j * rng.standard_normal((12, 12))
+    Ax = nud.forward_separable(x, kx, ky, X, Y)
+    Ahy = nud.adjoint(y, kx, ky, X, Y)
+    lhs = np.vdot(y, Ax)
+    rhs = np.vdot(Ahy, x)
+    return abs(lhs - rhs) / (np.linalg.norm(Ax) * np.linalg.norm(y))
+
+
+def test_k3_adjoint_identity():
+    assert check_adjoint() < 1e-13
+
+
+@pytest.mark.parametrize("weighting", [pipeline.WEIGHT_NONE, pipeline.WEIGHT_QUAD,
+                                       pipeline.WEIGHT_TFFR, pipeline.WEIGHT_FFR])
+def test_k3_pipeline_adjoint_all_modes(weighting):
+    """Re<I(s), y> = Re<s, grad_s> for the loss L = Re<I, y> (grad_I = y)."""
+    rng = np.random.default_rng(4)
+    prob = _tiny_problem(6, 10, 12, weighting=weighting)
+    phase = rng.normal(0, 0.5, 6)
+    dal = rng.normal(0, 0.01, 6)
+    s = rng.standard_normal((6, 10)) + 1j * rng.standard_normal((6, 10))
+    y = rng.standard_normal((12, 12)) + 1j * rng.standard_normal((12, 12))
+    I = pipeline.image(prob, s, phase, dal)
+    gs, _, _ = pipeline.backward(prob, y, s, phase, dal)
+    lhs = np.real(np.vdot(y, I))
+    rhs = np.real(np.vdot(gs, s))
+    assert abs(lhs - rhs) / (np.linalg.norm(I) * np.linalg.norm(y)) < 1e-13
+
+
+# ---------------------------------------------------------------- K4: brute force
+def brute_force_image(c, kx, ky, X, Y):
+    out = np.zeros((len(X), len(Y)), complex)
+    for jx in range(len(X)):
+        for jy in range(len(Y)):
+            acc = 0j
+            for n in range(c.shape[0]):
+                for p in range(c.shape[1]):
+                    acc += c[n, p] * complex(np.exp(1j * (kx[n, p] * X[jx] + ky[n] * Y[jy])))
+            out[jx, jy] = acc
+    return out
+
+
+def test_k4_forms_match_brute_force():
+    rng = np.random.default_rng(5)
+    prob = _tiny_problem(8, 16, 16)
+    kx, ky, lam, X, Y = prob.geometry()
+    c = rng.standard_normal(kx.shape) + 1j * rng.standard_normal(kx.shape)
+    ref = brute_force_image(c, kx, ky, X, Y)
+    # the phases reach |kx X| ~ 8.6e3 rad, so forms that round the phase differently
+    # (one exponential of a sum vs a product of two) agree to ~ 4 eps max|phase|
+    tol = 4 * np.finfo(float).eps * np.max(np.abs(kx)) * np.max(np.abs(X)) * 2
+    assert _rel(nudft.forward_direct(c, kx, ky, X, Y), ref) < tol
+    assert _rel(nudft.forward_separable(c, kx, ky, X, Y), ref) < tol
+    cols = [0, 5, 15]
+    assert _rel(nudft.forward_columns(c, kx, ky, X, Y, cols), ref[cols]) < tol
+    pix = [(0, 0), (3, 7), (15, 15)]
+    assert _rel(nudft.forward_pixels(c, kx, ky, X, Y, pix), np.array([ref[p] for p in pix])) < tol
+    # adjoint at single samples against the brute-force conjugate transpose
+    y = rng.standard_normal((16, 16)) + 1j * rng.standard_normal((16, 16))
+    full = nudft.adjoint(y, kx, ky, X, Y)
+    for (n, p) in [(0, 0), (3, 9), (7, 15)]:
+        acc = sum(y[jx, jy] * np.exp(-1j * (kx[n, p] * X[jx] + ky[n] * Y[jy]))
+                  for jx in range(16) for jy in range(16))
+        assert abs(full[n, p] - acc) / abs(acc) < 50 * tol
+    got = nudft.adjoint_samples(y, kx, ky, X, Y, [(3, 9)])
+    assert abs(got[0] - full[3, 9]) / abs(full[3, 9]) < 50 * tol
+
+
+# ---------------------------------------------------------------- K5: window transforms
+def _quad_complex(f, lo, hi, points=None):
+    re = integrate.quad(lambda x: np.real(f(x)), lo, hi, points=points, epsabs=1e-15, epsrel=1e-14, limit=400)[0]
+    im = integrate.quad(lambda x: np.imag(f(x)), lo, hi, points=points, epsabs=1e-15, epsrel=1e-14, limit=400)[0]
+    return re + 1j * im
+
+
+def check_window_transforms(win=window, a=0.01):
+    """Quadrature of the defining integrals on the un-centred unit interval:
+    w_hat(d) = int_0^1 w(x) e^{-2 pi i d x} dx = e^{-i pi d} R_W(d) and
+    <e^{2 pi i lam x}, e^{2 pi i l x}/w(x)> = e^{-i pi (l - lam)} R_Psi(l - lam)."""
+    worst = 0.0
+    for d in [0.0, 0.13, 0.5, 0.97, 1.0, 1.5, 2.37, -2.9, 3.0]:
+        w_hat = _quad_complex(lambda x: np.exp(-a * abs(x - 0.5)) * np.exp(-2j * np.pi * d * x), 0, 1, [0.5])
+        psi = _quad_complex(lambda x: np.exp(a * abs(x - 0.5)) * np.exp(-2j * np.pi * d * x), 0, 1, [0.5])
+        worst = max(worst, abs(np.exp(-1j * np.pi * d) * win.r_w(d, a) - w_hat))
+        worst = max(worst, abs(np.exp(-1j * np.pi * d) * win.r_psi(d, a) - psi))
+    return worst
+
+
+def test_k5_window_closed_forms_vs_quadrature():
+    assert check_window_transforms() < 1e-13
+    assert check_window_transforms(a=0.7) < 1e-13
+
+
+def test_k5_window_function():
+    x = np.linspace(0, 1, 11)
+    assert np.allclose(window.window(x, 0.01), np.exp(-0.01 * np.abs(x - 0.5)), rtol=0, atol=0)
+
+
+# ---------------------------------------------------------------- K6: limits
+def test_k6_small_a_limit_is_sinc():
+    """|exp(+-a|t|) - 1| <= a/2 (1 + a) on |t| <= 1/2, so |R(d) - sinc(d)| <= a/2 (1 + a);
+    the closed forms lose ~eps/a at d = 0 to cancellation, hence a = 1e-7."""
+    d = np.linspace(-4.3, 4.3, 37)
+    a = 1e-7
+    for f in (window.r_w, window.r_psi):
+        assert np.max(np.abs(f(d, a) - np.sinc(d))) < a / 2 * (1 + a) + 1e-8
+
+
+def test_k6_parseval_large_q():
+    """sum over all m of R_Psi(m-lam) R_W(m-lam) = int w (1/w) = 1 (Parseval on the unit
+    interval), and the tail beyond |m - lam| >= q decays like 1/q, so the truncated
+    diagonal converges to 1 at that rate."""
+    lam = np.array([0.0, 0.25, 0.5, 0.8, 1234.37])
+    err = {q: np.abs(weights.frame_diagonal(lam, 0.01, q) - 1.0) for q in (30, 300, 3000)}
+    assert np.max(err[3000]) < 1e-4
+    big = err[30] > 1e-9  # off-lattice samples: the tail is O(1/q)
+    assert np.all(err[300][big] < err[30][big] / 5) and np.all(err[3000][big] < err[300][big] / 5)
+    # on the lattice (lam integer) every tap but m = lam vanishes to O(a): g(0) ~ 1
+    assert abs(weights.frame_diagonal(np.array([7.0]), 0.01, 3)[0] - 1.0) < 1e-6
+
+
+def test_k6_gram_limit_is_sinc_gram():
+    """q -> infinity and a -> 0: the frame product is the Gram matrix of Fourier modes on
+    the unit interval, sinc(lam_p - lam_p')."""
+    lam = np.array([10.1, 11.4, 12.95, 14.2, 15.0])
+    G = weights.frame_product_row(lam, a=1e-12, q=2000)
+    ref = np.sinc(lam[:, None] - lam[None, :])
+    assert np.max(np.abs(G - ref)) < 5e-4
+
+
+def test_k6_frame_diagonal_depends_on_fraction_only():
+    lam = np.array([0.3, 7.3, 12345.3, -4.7])
+    g = weights.frame_diagonal(lam, 0.01, 3)
+    assert np.max(np.abs(g - g[0])) < 1e-12
+
+
+# ---------------------------------------------------------------- K7: FFR
+def test_k7_frame_reconstruction_full_band():
+    """With the exact Gram matrix and a full band, D f_hat returns the coefficients of a
+    function in the span of the frame (f = sum_p c_p e^{2 pi i lam_p t}, whose data are
+    f_hat(lam_p') = sum_p c_p sinc(lam_p - lam_p'))."""
+    rng = np.random.default_rng(7)
+    lam = np.cumsum(rng.uniform(1.2, 1.9, 9)) + 20.0
+    c = rng.standard_normal(9) + 1j * rng.standard_normal(9)
+    f_hat = np.sinc(lam[None, :] - lam[:, None]) @ c
+    D = weights.ffr_weights_row(lam, a=1e-13, q=4000, r=8)
+    assert np.max(np.abs(D @ f_hat - c)) / np.max(np.abs(c)) < 2e-3
+
+
+def test_k7_band_is_band_of_pinv():
+    k, ku = scenes.radar_sampling(4, 32)
+    kx, ky = geometry.stolt(k, ku)
+    lam = geometry.lattice_coordinate(kx, 40.0)
+    band = weights.ffr_weights(lam, 0.01, 3, 2)
+    for n in range(4):
+        Z = np.linalg.pinv(weights.frame_product_row(lam[n], 0.01, 3))
+        Dn = weights.band_to_dense(band[n])
+        for p in range(32):
+            for pp in range(32):
+                want = Z[p, pp] if abs(p - pp) <= 2 else 0.0
+                assert Dn[p, pp] == want
+
+
+def test_k7_frame_product_is_banded_and_near_identity():
+    k, ku = scenes.radar_sampling(2, 64)
+    kx, _ = geometry.stolt(k, ku)
+    lam = geometry.lattice_coordinate(kx, 40.0)
+    G = weights.frame_product_row(lam[0], 0.01, 3)
+    sep = np.abs(lam[0][:, None] - lam[0][None, :])
+    assert np.all(G[sep >= 6.0] == 0.0)
+    assert np.allclose(np.diag(G), weights.frame_diagonal(lam[0], 0.01, 3), rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------- K8: threshold
+def test_k8_threshold_invariants():
+    rng = np.random.default_rng(8)
+    lam = rng.uniform(0, 500, 2000)
+    g = weights.frame_diagonal(lam, 0.01, 3)
+    inv = 1.0 / g
+    d, kept = weights.tffr_weights(lam, 0.01, 3, tau=inv.min())
+    assert kept.all()
+    d, kept = weights.tffr_weights(lam, 0.01, 3, tau=np.nextafter(inv.max(), np.inf))
+    assert not kept.any() and np.all(d == 0)
+    counts = [weights.tffr_weights(lam, 0.01, 3, tau=t)[1].sum() for t in np.linspace(0.9, 1.3, 41)]
+    assert all(b <= a for a, b in zip(counts, counts[1:]))
+    # the paper's tau = 0.97 under the literal reading keeps every sample: the truncated
+    # diagonal g never exceeds 1 by more than O(a^2), so 1/g > 0.97
+    d, kept = weights.tffr_weights(lam, 0.01, 3, tau=0.97)
+    assert kept.all() and np.all(d >= 1.0 - 1e-6)
+    # correlation mode: monotone the other way round and a strict subset at tau = 0.97
+    counts1 = [weights.tffr_weights(lam, 0.01, 3, tau=t, mode=weights.THRESH_CORRELATION)[1].sum()
+               for t in np.linspace(0.8, 1.0, 21)]
+    assert all(b <= a for a, b in zip(counts1, counts1[1:]))
+    assert 0 < counts1[-4] < lam.size
+
+
+def test_k8_zero_image_above_max():
+    rng = np.random.default_rng(81)
+    prob = _tiny_problem(4, 8, 8, tau=10.0)
+    s = rng.standard_normal((4, 8)) + 0j
+    assert np.all(pipeline.image(prob, s) == 0)
+
+
+def test_k8_inclusive_threshold():
+    lam = np.array([0.37])
+    inv = 1.0 / weights.frame_diagonal(lam, 0.01, 3)[0]
+    assert weights.tffr_weights(lam, 0.01, 3, tau=inv)[1][0]
+    assert not weights.tffr_weights(lam, 0.01, 3, tau=np.nextafter(inv, 2))[1][0]
+
+
+# ---------------------------------------------------------------- K9: quadrature
+def test_k9_trapezoid_uniform():
+    lam = 3.0 + 0.75 * np.arange(10)
+    q = weights.quad_weights(lam[None, :])[0]
+    assert np.allclose(q[1:-1], 0.75, rtol=0, atol=1e-14)
+    assert np.allclose([q[0], q[-1]], 0.375, rtol=0, atol=1e-14)
+    # integrates a linear function exactly with the trapezoid rule over the sample span
+    f = 2.0 * lam + 1.0
+    assert abs(np.sum(q * f) - ((lam[-1] ** 2 + lam[-1]) - (lam[0] ** 2 + lam[0]))) < 1e-12
+
+
+# ---------------------------------------------------------------- K10: gradients
+def _loss(prob, s, phase, dal):
+    return entropy.entropy(pipeline.image(prob, s, phase, dal))
+
+
+def test_k10_entropy_gradient_fd():
+    rng = np.random.default_rng(10)
+    I = rng.standard_normal((6, 5)) + 1j * rng.standard_normal((6, 5))
+    g = entropy.entropy_grad(I)
+    h = 1e-6
+    for idx in [(0, 0), (2, 3), (5, 4)]:
+        for part, unit in (("re", 1.0), ("im", 1j)):
+            Ip = I.copy(); Ip[idx] += h * unit
+            Im = I.copy(); Im[idx] -= h * unit
+            fd = (entropy.entropy(Ip) - entropy.entropy(Im)) / (2 * h)
+            an = g[idx].real if part == "re" else g[idx].imag
+            assert abs(fd - an) < 1e-7 * max(1.0, abs(an))
+
+
+def test_k10_entropy_known_values():
+    """Uniform magnitudes over K pixels: E = ln K; one non-zero pixel: E = 0."""
+    assert abs(entropy.entropy(np.ones((4, 8)) * (1 + 1j)) - np.log(32)) < 1e-13
+    z = np.zeros((4, 4), complex); z[1, 2] = 3 - 1j
+    assert abs(entropy.entropy(z)) < 1e-15
+    assert np.all(entropy.entropy_grad(z) == 0)
+
+
+@pytest.mark.parametrize("weighting", [pipeline.WEIGHT_TFFR, pipeline.WEIGHT_FFR])
+def test_k10_pipeline_gradients_central_fd(weighting):
+    """Central differences (h = 1e-4) of the entropy loss on the FP64 oracle agree with
+    the adjoint-based gradient; a global phase leaves |I| unchanged (sum dE/dphi = 0)."""
+    rng = np.random.default_rng(11)
+    prob = _tiny_problem(6, 12, 12, weighting=weighting)
+    kx, ky, lam, X, Y = prob.geometry()
+    s = rng.standard_normal((6, 12)) + 1j * rng.standard_normal((6, 12))
+    phase = rng.normal(0, 0.5, 6)
+    dal = rng.normal(0, 0.003, 6)
+    I = pipeline.image(prob, s, phase, dal)
+    gI = entropy.entropy_grad(I)
+    gs, gphi, gdal = pipeline.backward(prob, gI, s, phase, dal)
+    h = 1e-4
+    for n in range(6):
+        e = np.zeros(6); e[n] = h
+        fd = (_loss(prob, s, phase + e, dal) - _loss(prob, s, phase - e, dal)) / (2 * h)
+        assert abs(fd - gphi[n]) <= 1e-6 * max(np.max(np.abs(gphi)), 1e-12)
+        e2 = np.zeros(6); e2[n] = h * 1e-3
+        fd2 = (_loss(prob, s, phase, dal + e2) - _loss(prob, s, phase, dal - e2)) / (2 * h * 1e-3)
+        assert abs(fd2 - gdal[n]) <= 1e-5 * max(np.max(np.abs(gdal)), 1e-12)
+    for (n, p) in [(0, 0), (3, 7), (5, 11)]:
+        for unit in (1.0, 1j):
+            sp = s.copy(); sp[n, p] += h * unit
+            sm = s.copy(); sm[n, p] -= h * unit
+            fd = (_loss(prob, sp, phase, dal) - _loss(prob, sm, phase, dal)) / (2 * h)
+            an = gs[n, p].real if unit == 1.0 else gs[n, p].imag
+            assert abs(fd - an) <= 1e-6 * max(np.max(np.abs(gs)), 1e-12)
+    assert abs(gphi.sum()) < 1e-12 * max(1.0, np.abs(gphi).sum())
+
+
+# ---------------------------------------------------------------- K11: commuting factors
+def test_k11_weighting_commutes_with_row_phase():
+    rng = np.random.default_rng(12)
+    for weighting in (pipeline.WEIGHT_TFFR, pipeline.WEIGHT_FFR, pipeline.WEIGHT_QUAD):
+        prob = _tiny_problem(5, 12, 8, weighting=weighting)
+        kx, ky, lam, X, Y = prob.geometry()
+        s = rng.standard_normal((5, 12)) + 1j * rng.standard_normal((5, 12))
+        psi = rng.normal(0, 1, 5)
+        w = pipeline.sample_weights(prob)
+        a = pipeline.apply_weights(w, s * np.exp(1j * psi)[:, None])
+        b = pipeline.apply_weights(w, s) * np.exp(1j * psi)[:, None]
+        assert np.max(np.abs(a - b)) < 1e-14
+
+
+# ---------------------------------------------------------------- geometry pins
+def test_stolt_is_stationary_phase_of_spherical_wave():
+    """The azimuth spectrum of a point target's two-way phase 2k sqrt(x0^2 + (y0-u)^2)
+    has, by stationary phase, phase kx x0 + ku y0 with kx the Stolt wavenumber."""
+    x0, y0 = 37.0, -4.0
+    k = np.array([203.5, 209.6, 215.7])
+    ku = np.array([-150.0, -20.0, 0.0, 90.0, 200.0])
+    kx, ky = geometry.stolt(k, ku)
+    for n in range(ku.size):
+        for p in range(k.size):
+            f = lambda u: 2 * k[p] * np.hypot(x0, y0 - u) + ku[n] * u
+            res = optimize.minimize_scalar(f, bracket=(-1000, 0, 1000), tol=1e-14)
+            assert abs(res.fun - (kx[n, p] * x0 + ky[n] * y0)) < 1e-8 * abs(res.fun)
+
+
+def test_geometry_validation_and_pixels():
+    with pytest.raises(geometry.GeometryError):
+        geometry.stolt([10.0, 11.0], [25.0])
+    with pytest.raises(geometry.GeometryError):
+        geometry.stolt([11.0, 10.0], [0.0])
+    X = geometry.pixel_coordinates(8, 4.0)
+    assert X[4] == 0.0 and np.allclose(np.diff(X), 0.5)
+
+
+def test_scene_focuses_at_scatterer():
+    """An image of a single synthetic scatterer (signal model in the input generator,
+    independent code) peaks at the scatterer's pixel."""
+    import dataclasses
+
+    wl = dataclasses.replace(scenes.WORKLOADS["tiny_ffr_c128"], n_scatterers=1, snr_db=None,
+                             n_pulses=32, n_freq=64, m=64)
+    rng = np.random.default_rng(99)
+    k, ku = scenes.radar_sampling(wl.n_pulses, wl.n_freq)
+    x0, y0 = 5.0, -7.5
+    kx, ky = geometry.stolt(k, ku)
+    s = np.exp(-1j * (kx * x0 + ky[:, None] * y0))
+    prob = pipeline.Problem(k=k, ku=ku, mx=64, my=64, fov_x=40.0, fov_y=40.0,
+                            weighting=pipeline.WEIGHT_NONE)
+    I = pipeline.image(prob, s)
+    jx, jy = np.unravel_index(np.argmax(np.abs(I)), I.shape)
+    assert (jx, jy) == (32 + 8, 32 - 12)
+    del rng
+
+
+# ---------------------------------------------------------------- paper constants
+def test_paper_constants_are_defaults():
+    gold = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
+    prob = _tiny_problem()
+    assert prob.a == gold["window_a"]
+    assert prob.tau == gold["tffr_tau"]
+    assert prob.r == gold["ffr_band_r"]
+
+
+# ---------------------------------------------------------------- mutation tests
+class _Patched:
+    def __init__(self, module, **repl):
+        self.m = module
+        self.repl = repl
+
+    def __getattr__(self, name):
+        return self.repl.get(name, getattr(self.m, name))
+
+
+def test_mutations_are_caught():
+    """Plausible mistakes planted in (copies of) the oracle fail at least one pin."""
+    # wrong sign of the exponent
+    bad = _Patched(nudft, forward_direct=lambda c, kx, ky, X, Y: np.conj(
+        nudft.forward_direct(np.conj(c), kx, ky, X, Y)))
+    assert check_dft_lattice(bad) > 1e-3
+    # transposed operand (range and azimuth swapped in the output)
+    bad = _Patched(nudft, forward_direct=lambda c, kx, ky, X, Y: nudft.forward_direct(c, kx, ky, X, Y).T)
+    assert check_dirichlet(bad) > 1e-3
+    # dropped term in the closed form of R_Psi
+    bad_win = _Patched(window, r_psi=lambda d, a: 2 * np.exp(a / 2) * (2 * np.pi * np.asarray(d)) * np.sin(np.pi * np.asarray(d))
+                       / (a * a + (2 * np.pi * np.asarray(d)) ** 2 + 1e-300))
+    assert check_window_transforms(bad_win) > 1e-4
+    # adjoint missing its conjugation
+    bad = _Patched(nudft, adjoint=lambda y, kx, ky, X, Y: np.conj(nudft.adjoint(np.conj(y), kx, ky, X, Y)))
+    assert check_adjoint(bad) > 1e-3
+
+
+def test_oracle_package_docstring_marks_test_infrastructure():
+    assert "TEST INFRASTRUCTURE ONLY" in oracle.__doc__
