@@ -1,0 +1,171 @@
+/*
+ * tffr.h -- C ABI of libtffr: thresholded non-uniform Fourier frame reconstruction
+ * (tFFR) of Stolt-mapped stripmap-SAR phase history on one AMD MI355X (gfx950).
+ *
+ * Method: McKay, Gelb, Jayasuriya, Monga, "Thresholded Non-Uniform Fourier
+ * Frame-Based Reconstruction for Stripmap SAR".  Algorithm 1 takes the Fourier data
+ * f_hat(lambda^1_n, lambda^2_p), the uniform grid {l_m} and a threshold tau > 0 and
+ * returns the SAR image; this library takes the phase-history samples, the radar
+ * wavenumbers that fix their coordinates, the weighting method with its window and
+ * threshold parameters, and returns the image (forward), the adjoint of that map
+ * (gradients), and an image-entropy loss.
+ *
+ * Conventions shared by every call:
+ *  - Samples are [n_pulses][n_freq], row-major: row n is one azimuth slice (pulse) at
+ *    azimuth wavenumber ku[n]; column p is fast-time wavenumber k[p].  Sample (n, p)
+ *    sits at kx = sqrt(4 k_p^2 - ku_n^2), ky = ku_n (Stolt map, Sec. II-A).
+ *  - Images are [mx][my], row-major and RANGE-MAJOR: element (jx, jy) is at offset
+ *    jx*my + jy and is the pixel at X = (jx - mx/2) fov_x/mx (range),
+ *    Y = (jy - my/2) fov_y/my (azimuth), both relative to the scene centre.
+ *  - The forward map is I[jx,jy] = sum_{n,p} c[n,p] exp(+i (kx X + ky Y)) with
+ *    c = D (s * exp(i (phase[n] + ky[n] dalong[n]))) and D the weights of the chosen
+ *    method (Eq. (1); Eqs. (3)-(4) and (8) reach it with the window truncated).
+ *    It is evaluated by gridding with an exponential-of-semicircle kernel of
+ *    kernel_width taps on a grid upsampfac times finer, inverse FFT, and division by
+ *    the kernel's transform.  No global normalisation is applied.
+ *  - Complex data are interleaved (re, im).  dtype TFFR_C64: float; TFFR_C128: double;
+ *    TFFR_C64_FP16IN: samples stored as two IEEE half values, everything else float.
+ *    "real" below means float for C64 / C64_FP16IN and double for C128.
+ *  - Device pointers are HIP device memory on the current device; the caller owns
+ *    every buffer it passes.  The plan owns only small device tables.
+ *  - Calls that take a stream only enqueue work on it and never synchronise, except
+ *    tffr_kept_count.  A plan is immutable after creation; concurrent calls on one
+ *    plan need separate workspaces.
+ *  - Every call returns a tffr_status; nothing throws or aborts across the ABI.
+ *    Argument and geometry errors are detected on the host before any launch.
+ */
+#ifndef TFFR_H
+#define TFFR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tffr_plan tffr_plan;
+typedef void *tffr_stream; /* a hipStream_t; NULL is the null stream */
+
+typedef enum {
+  TFFR_OK = 0,
+  TFFR_ERR_ARG = 1,          /* bad size, pointer or parameter value               */
+  TFFR_ERR_EVANESCENT = 2,   /* some sample has 4 k^2 <= ku^2                       */
+  TFFR_ERR_NONMONOTONE = 3,  /* k is not strictly increasing                        */
+  TFFR_ERR_LAYOUT = 4,       /* buffer too small / misaligned                       */
+  TFFR_ERR_UNSUPPORTED = 5,  /* width, dtype, grid size or FFR band not supported   */
+  TFFR_ERR_SINGULAR = 6,     /* plain-FFR frame product has a vanishing pivot       */
+  TFFR_ERR_NOMEM = 7,        /* device or host allocation of plan tables failed     */
+  TFFR_ERR_HIP = 8           /* a HIP runtime call failed                           */
+} tffr_status;
+
+/* Weighting methods: the alpha_n / D of Eqs. (1), (4) and (8). */
+enum {
+  TFFR_W_NONE = 0, /* D = I                                                          */
+  TFFR_W_QUAD = 1, /* trapezoid quadrature in lambda along each slice (Sec. II-B)     */
+  TFFR_W_FFR = 2,  /* plain FFR: D = B_r(pinv(Psi W)) per slice (Eq. (8))              */
+  TFFR_W_TFFR = 3, /* tFFR: D = R_tau(pinv(diag(Psi W))) (Sec. III-B, III-C)           */
+  TFFR_W_USER = 4  /* caller-supplied diagonal weights                                */
+};
+
+/* What R_tau compares (Sec. III-B): the entries of the inverted diagonal as written
+ * (keep iff 1/g >= tau), or the correlation g itself (keep iff g >= tau). */
+enum { TFFR_THRESH_LITERAL = 0, TFFR_THRESH_CORRELATION = 1 };
+
+enum { TFFR_C64 = 0, TFFR_C128 = 1, TFFR_C64_FP16IN = 2 };
+
+typedef struct {
+  int32_t n_pulses;     /* slices n (azimuth), >= 1                                   */
+  int32_t n_freq;       /* samples p per slice (fast-time frequency), >= 1            */
+  int32_t mx, my;       /* image size (range, azimuth), even, 2..16384               */
+  double fov_x, fov_y;  /* scene extents in metres, > 0                               */
+  int32_t weighting;    /* TFFR_W_*                                                   */
+  double window_a;      /* w(x) = exp(-a |x - 1/2|), a = 0.01 in Sec. IV; >= 0        */
+  double q;             /* truncation of W and Psi in lattice units, >= 1 (default 3) */
+  int32_t band_r;       /* plain-FFR band B_r, r = 2 in Sec. IV; 0..8                 */
+  double tau;           /* threshold, tau = 0.97 in Sec. IV; > 0                      */
+  int32_t thresh_mode;  /* TFFR_THRESH_*                                              */
+  int32_t kernel_width; /* gridding taps: 2..16 (7 gives ~1e-6 relative error)        */
+  double upsampfac;     /* fine grid >= upsampfac * image size, rounded up to 2^k; 1.25..4 */
+  int32_t dtype;        /* TFFR_C64, TFFR_C128, TFFR_C64_FP16IN                        */
+} tffr_params;
+
+/* Paper defaults: a = 0.01, tau = 0.97, r = 2 (Sec. IV, Baselines); q = 3, tFFR with
+ * the literal threshold, width 7, upsampfac 2, complex64.  Sizes are set to 0. */
+void tffr_default_params(tffr_params *p);
+
+/* Host-only check of params and geometry; no HIP call.  k: host [n_freq] rad/m,
+ * ku: host [n_pulses] rad/m.  Returns the status tffr_plan_create would return for
+ * these arguments before touching the device. */
+tffr_status tffr_validate(const tffr_params *p, const double *k, const double *ku);
+
+/* Create a plan on the current HIP device.  k and ku are copied.  Builds the device
+ * tables (kernel deapodisation, twiddles, per-slice azimuth taps, tFFR weight
+ * polynomial) and, for TFFR_W_FFR, checks that the band fits (TFFR_ERR_UNSUPPORTED).
+ * Synchronises the device once.  *out is NULL on error. */
+tffr_status tffr_plan_create(const tffr_params *p, const double *k, const double *ku,
+                             tffr_plan **out);
+
+void tffr_plan_destroy(tffr_plan *plan);
+
+/* Bytes of caller-owned device workspace every forward / adjoint / entropy / weights
+ * call needs (the per-slice range spectra plus reduction scratch).  0 for NULL. */
+size_t tffr_workspace_bytes(const tffr_plan *plan);
+
+/* Sizes chosen by the plan: fine grid in range and azimuth, ES kernel shape beta,
+ * plain-FFR half-bandwidth of the frame product (0 for other methods). */
+tffr_status tffr_plan_info(const tffr_plan *plan, int32_t *nfine_x, int32_t *nfine_y,
+                           double *beta, int32_t *ffr_halfband);
+
+/* Materialise the weights of the plan's method into d_w (device, real):
+ *   diagonal methods: [n_pulses][n_freq];  TFFR_W_FFR: [n_pulses][n_freq][2r+1] with
+ *   entry [n][p][r+o] = D_{p,p+o} of slice n (0 past the row ends).
+ * TFFR_W_USER is rejected (TFFR_ERR_ARG).  Enqueued on `stream`. */
+tffr_status tffr_weights(tffr_plan *plan, void *d_w, void *d_work, tffr_stream stream);
+
+/* Number c of samples the threshold keeps (Sec. III-C), computed on the device and
+ * copied to *count.  Synchronises `stream`.  For non-tFFR methods c = n_pulses*n_freq. */
+tffr_status tffr_kept_count(tffr_plan *plan, void *d_work, int64_t *count, tffr_stream stream);
+
+/* Forward (image formation):
+ *   d_samples  [n_pulses][n_freq] complex (dtype), read only
+ *   d_phase    [n_pulses] real, per-pulse phase error phi in rad, or NULL (zeros)
+ *   d_dalong   [n_pulses] real, along-track position error du in m, or NULL (zeros)
+ *   d_user_w   NULL to compute the plan's weights on the fly; otherwise weights in the
+ *              layout of tffr_weights (required for TFFR_W_USER)
+ *   d_image    [mx][my] complex, written (range-major)
+ *   d_work     tffr_workspace_bytes() bytes of device scratch */
+tffr_status tffr_forward(tffr_plan *plan, const void *d_samples, const void *d_phase,
+                         const void *d_dalong, const void *d_user_w, void *d_image,
+                         void *d_work, tffr_stream stream);
+
+/* Adjoint / backward of tffr_forward for a real loss L(I):
+ *   d_grad_image   [mx][my] complex, dL/dRe I + i dL/dIm I, read only
+ *   d_samples      [n_pulses][n_freq] complex (dtype); needed only when d_grad_phase or
+ *                  d_grad_dalong is non-NULL, else may be NULL
+ *   d_phase, d_dalong, d_user_w as in tffr_forward
+ *   d_grad_samples [n_pulses][n_freq] complex (float for C64/C64_FP16IN), written:
+ *                  exp(-i psi_n) D^T A^H grad_image
+ *   d_grad_phase   [n_pulses] real or NULL: dL/dphi_n = sum_p Re(conj(g'_np) i s'_np)
+ *   d_grad_dalong  [n_pulses] real or NULL: ky_n dL/dphi_n
+ * With the gradient outputs NULL this is the plain adjoint operator A'^H. */
+tffr_status tffr_adjoint(tffr_plan *plan, const void *d_grad_image, const void *d_samples,
+                         const void *d_phase, const void *d_dalong, const void *d_user_w,
+                         void *d_grad_samples, void *d_grad_phase, void *d_grad_dalong,
+                         void *d_work, tffr_stream stream);
+
+/* Image entropy E = -sum p_j ln p_j, p_j = |I_j|^2 / sum |I|^2, the focus criterion
+ * for autofocus-style refinement (the paper's TBED of Eq. (10) uses region entropies):
+ *   d_image       [mx][my] complex, read only
+ *   d_loss        device double[1], written
+ *   d_grad_image  [mx][my] complex or NULL: -(2/S)(ln p_j + E) I_j (0 where I_j = 0) */
+tffr_status tffr_entropy(tffr_plan *plan, const void *d_image, double *d_loss,
+                         void *d_grad_image, void *d_work, tffr_stream stream);
+
+const char *tffr_status_string(tffr_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TFFR_H */

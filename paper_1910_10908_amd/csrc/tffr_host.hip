@@ -1,0 +1,627 @@
+// Host side of libtffr: parameter and geometry validation, plan tables, workspace
+// layout and the C ABI entry points declared in include/tffr.h and tffr_debug.h.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "tffr.h"
+#include "tffr_debug.h"
+#include "tffr_internal.h"
+
+using tffr::cplx;
+
+namespace {
+
+constexpr double kPi = 3.141592653589793;
+constexpr int kMaxLogN = 14;
+constexpr int kMaxHalfBand = 16;
+constexpr int kPartials = 1024;  // reduction blocks for entropy / kept count
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// ---------------------------------------------------------------- window transforms
+// Same closed forms as the device code: centred finite-interval cosine transforms of
+// exp(-a|t|) and exp(+a|t|) over [-1/2, 1/2].
+double r_w(double d, double a) {
+  const double b = 2.0 * kPi * d, den = a * a + b * b;
+  if (den == 0.0) return 1.0;
+  return 2.0 * (a + std::exp(-a / 2.0) * (b * std::sin(b / 2.0) - a * std::cos(b / 2.0))) / den;
+}
+double r_psi(double d, double a) {
+  const double b = 2.0 * kPi * d, den = a * a + b * b;
+  if (den == 0.0) return 1.0;
+  return 2.0 * (std::exp(a / 2.0) * (b * std::sin(b / 2.0) + a * std::cos(b / 2.0)) - a) / den;
+}
+// diagonal of the truncated frame product at fractional lattice offset delta
+double frame_diag(double delta, double a, double q) {
+  const int K = (int)std::ceil(q) + 1;
+  double acc = 0.0;
+  for (int k = -K; k <= K; ++k) {
+    const double d = (double)k - delta;
+    if (std::fabs(d) < q) acc += r_psi(d, a) * r_w(d, a);
+  }
+  return acc;
+}
+
+// ---------------------------------------------------------------- ES kernel tables
+double es(double z, double beta) {
+  const double s = 1.0 - z * z;
+  return s > 0.0 ? std::exp(beta * (std::sqrt(s) - 1.0)) : 0.0;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton iteration on P_n).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5)), pp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p1 = 1.0, p2 = 0.0;
+      for (int j = 1; j <= n; ++j) {
+        const double p3 = p2;
+        p2 = p1;
+        p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+      }
+      pp = n * (z * p1 - p2) / (z * z - 1.0);
+      const double dz = p1 / pp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * pp * pp);
+  }
+}
+
+// 1 / (continuous Fourier transform of the kernel) at the centred bins j - m/2 of a
+// length-nfine periodic grid: phihat(j) = (W/2) int_{-1}^{1} es(z) cos(2 pi j (W/2) z / nfine) dz.
+std::vector<double> deapod_table(int m, int nfine, int W, double beta) {
+  std::vector<double> x, wq;
+  gauss_legendre(std::max(200, 4 * W + 64), x, wq);
+  std::vector<double> out(m);
+  for (int jj = 0; jj < m; ++jj) {
+    const double j = jj - m / 2;
+    double acc = 0.0;
+    for (size_t i = 0; i < x.size(); ++i)
+      acc += wq[i] * es(x[i], beta) * std::cos(2.0 * kPi * j * (W / 2.0) * x[i] / nfine);
+    out[jj] = 1.0 / ((W / 2.0) * acc);
+  }
+  return out;
+}
+
+int log2_pow2_at_least(double v) {
+  int l = 0;
+  while ((double)(1 << l) < v - 1e-9) ++l;
+  return l;
+}
+
+// ---------------------------------------------------------------- plan
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+struct tffr_plan {
+  tffr_params prm;
+  int device = 0;
+  tffr::Geo geo{};
+  int cb = 1;  // range columns per workgroup in the azimuth stage
+  int ffr_halfband = 0;
+  double beta = 0.0;
+  // device tables
+  DevBuf k, ku, ky, ystart, ytap, deapx, deapy, twx, twy, poly, ffr_d;
+  // workspace layout
+  size_t off_hx = 0, off_part = 0, off_kept = 0, off_count = 0, off_status = 0, off_gband = 0, off_zband = 0,
+         off_dband = 0, work_bytes = 0;
+  bool dbl() const { return prm.dtype == TFFR_C128; }
+  size_t csize() const { return dbl() ? 16 : 8; }
+  size_t rsize() const { return dbl() ? 8 : 4; }
+};
+
+namespace {
+
+tffr_status hip_status(hipError_t e) { return e == hipSuccess ? TFFR_OK : TFFR_ERR_HIP; }
+
+template <typename T>
+tffr_status upload(DevBuf& b, const std::vector<T>& v) {
+  if (v.empty()) return TFFR_OK;
+  if (hipMalloc(&b.p, v.size() * sizeof(T)) != hipSuccess) return TFFR_ERR_NOMEM;
+  return hip_status(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+template <typename R>
+std::vector<R> cast(const std::vector<double>& v) {
+  return std::vector<R>(v.begin(), v.end());
+}
+
+template <typename R>
+tffr::Tab<R> tables(const tffr_plan* P) {
+  tffr::Tab<R> t;
+  t.k = (const double*)P->k.p;
+  t.ku = (const double*)P->ku.p;
+  t.ky = (const R*)P->ky.p;
+  t.ystart = (const int32_t*)P->ystart.p;
+  t.ytap = (const R*)P->ytap.p;
+  t.deapx = (const R*)P->deapx.p;
+  t.deapy = (const R*)P->deapy.p;
+  t.twx = (const cplx<R>*)P->twx.p;
+  t.twy = (const cplx<R>*)P->twy.p;
+  t.poly = (const float*)P->poly.p;
+  return t;
+}
+
+int sample_type(const tffr_plan* P) {
+  return P->prm.dtype == TFFR_C128 ? tffr::ST_C128 : (P->prm.dtype == TFFR_C64_FP16IN ? tffr::ST_H2 : tffr::ST_C64);
+}
+
+// Piecewise polynomial of 1/g(delta) on (0, 1) for the FP32 path: nseg segments, local
+// variable t in [-1, 1], monomial coefficients (highest first) from interpolation at
+// Chebyshev points.  Returns false when the fit misses 2e-8 relative somewhere.
+bool fit_weight_poly(double a, double q, int nseg, int deg, std::vector<float>& out) {
+  out.assign((size_t)nseg * (deg + 1), 0.0f);
+  const int np = deg + 1;
+  std::vector<double> tn(np), fv(np), A((size_t)np * np), c(np);
+  for (int s = 0; s < nseg; ++s) {
+    for (int i = 0; i < np; ++i) {
+      tn[i] = std::cos(kPi * (2.0 * i + 1.0) / (2.0 * np));
+      const double delta = (s + 0.5 * (tn[i] + 1.0)) / nseg;
+      fv[i] = 1.0 / frame_diag(delta, a, q);
+      for (int j = 0; j < np; ++j) A[(size_t)i * np + j] = std::pow(tn[i], deg - j);
+    }
+    // Gaussian elimination with partial pivoting on the small Vandermonde system
+    std::vector<double> M(A), rhs(fv);
+    for (int col = 0; col < np; ++col) {
+      int piv = col;
+      for (int r = col + 1; r < np; ++r)
+        if (std::fabs(M[(size_t)r * np + col]) > std::fabs(M[(size_t)piv * np + col])) piv = r;
+      for (int j = 0; j < np; ++j) std::swap(M[(size_t)col * np + j], M[(size_t)piv * np + j]);
+      std::swap(rhs[col], rhs[piv]);
+      for (int r = col + 1; r < np; ++r) {
+        const double l = M[(size_t)r * np + col] / M[(size_t)col * np + col];
+        for (int j = col; j < np; ++j) M[(size_t)r * np + j] -= l * M[(size_t)col * np + j];
+        rhs[r] -= l * rhs[col];
+      }
+    }
+    for (int r = np - 1; r >= 0; --r) {
+      double v = rhs[r];
+      for (int j = r + 1; j < np; ++j) v -= M[(size_t)r * np + j] * c[j];
+      c[r] = v / M[(size_t)r * np + r];
+    }
+    for (int j = 0; j < np; ++j) out[(size_t)s * np + j] = (float)c[j];
+    for (int i = 0; i <= 32; ++i) {
+      const double t = -1.0 + i / 16.0, delta = (s + 0.5 * (t + 1.0)) / nseg;
+      if (delta <= 0.0 || delta >= 1.0) continue;
+      double v = 0.0;
+      for (int j = 0; j < np; ++j) v = v * t + c[j];
+      const double ex = 1.0 / frame_diag(delta, a, q);
+      if (std::fabs(v - ex) > 2e-8 * std::fabs(ex)) return false;
+    }
+  }
+  return true;
+}
+
+tffr_status check_params(const tffr_params* p) {
+  if (!p) return TFFR_ERR_ARG;
+  if (p->n_pulses < 1 || p->n_freq < 1) return TFFR_ERR_ARG;
+  if (p->mx < 2 || p->my < 2 || (p->mx & 1) || (p->my & 1)) return TFFR_ERR_ARG;
+  if (p->mx > (1 << kMaxLogN) || p->my > (1 << kMaxLogN)) return TFFR_ERR_UNSUPPORTED;
+  if (!(p->fov_x > 0.0) || !(p->fov_y > 0.0) || !std::isfinite(p->fov_x) || !std::isfinite(p->fov_y))
+    return TFFR_ERR_ARG;
+  if (p->weighting < TFFR_W_NONE || p->weighting > TFFR_W_USER) return TFFR_ERR_ARG;
+  if (!(p->window_a >= 0.0) || !std::isfinite(p->window_a)) return TFFR_ERR_ARG;
+  if (!(p->q >= 1.0) || !(p->q <= 64.0)) return TFFR_ERR_ARG;
+  if (p->band_r < 0 || p->band_r > 8) return TFFR_ERR_ARG;
+  if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return TFFR_ERR_ARG;
+  if (p->thresh_mode != TFFR_THRESH_LITERAL && p->thresh_mode != TFFR_THRESH_CORRELATION) return TFFR_ERR_ARG;
+  if (p->kernel_width < 2 || p->kernel_width > 16) return TFFR_ERR_UNSUPPORTED;
+  if (!(p->upsampfac >= 1.25) || !(p->upsampfac <= 4.0)) return TFFR_ERR_UNSUPPORTED;
+  if (p->dtype != TFFR_C64 && p->dtype != TFFR_C128 && p->dtype != TFFR_C64_FP16IN) return TFFR_ERR_UNSUPPORTED;
+  const int lx = log2_pow2_at_least(p->upsampfac * p->mx), ly = log2_pow2_at_least(p->upsampfac * p->my);
+  if (std::max(lx, 6) > kMaxLogN || std::max(ly, 6) > kMaxLogN) return TFFR_ERR_UNSUPPORTED;
+  return TFFR_OK;
+}
+
+// Half bandwidth of the frame product: the largest |p - p'| whose windows
+// (lam - q, lam + q) share an integer, over all slices (plus one for rounding).
+int ffr_halfband(const tffr_params* p, const double* k, const double* ku) {
+  int b = 0;
+  std::vector<double> lam(p->n_freq);
+  for (int n = 0; n < p->n_pulses; ++n) {
+    for (int i = 0; i < p->n_freq; ++i) lam[i] = std::sqrt(4.0 * (k[i] * k[i]) - ku[n] * ku[n]) * p->fov_x / (2.0 * kPi);
+    int j = 0;
+    for (int i = 0; i < p->n_freq; ++i) {
+      const double top = std::ceil(lam[i] + p->q) - 1.0;  // largest integer < lam + q
+      if (j < i) j = i;
+      while (j + 1 < p->n_freq && std::floor(lam[j + 1] - p->q) + 1.0 <= top) ++j;
+      b = std::max(b, j - i);
+    }
+  }
+  return b + 1;
+}
+
+}  // namespace
+
+namespace {
+
+template <typename R>
+tffr_status do_forward(tffr_plan* P, const void* smp, const void* ph, const void* da, const void* uw, void* img,
+                       void* work, hipStream_t st, int stage_only) {
+  const tffr::Tab<R> t = tables<R>(P);
+  const R* w = (const R*)uw;
+  if (!w && P->prm.weighting == TFFR_W_FFR) w = (const R*)P->ffr_d.p;
+  cplx<R>* hx = (cplx<R>*)((char*)work + P->off_hx);
+  if (stage_only >= 0)
+    return hip_status(tffr::launch_fwd_rows<R>(P->geo, t, sample_type(P), smp, (const R*)ph, (const R*)da, w,
+                                               (cplx<R>*)img, stage_only, st));
+  hipError_t e = tffr::launch_fwd_rows<R>(P->geo, t, sample_type(P), smp, (const R*)ph, (const R*)da, w, hx, 1, st);
+  if (e == hipSuccess) e = tffr::launch_fwd_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, st);
+  return hip_status(e);
+}
+
+template <typename R>
+tffr_status do_adjoint(tffr_plan* P, const void* cot, const void* smp, const void* ph, const void* da, const void* uw,
+                       void* gs, void* gph, void* gda, void* work, hipStream_t st) {
+  const tffr::Tab<R> t = tables<R>(P);
+  const R* w = (const R*)uw;
+  if (!w && P->prm.weighting == TFFR_W_FFR) w = (const R*)P->ffr_d.p;
+  cplx<R>* hx = (cplx<R>*)((char*)work + P->off_hx);
+  hipError_t e = tffr::launch_adj_cols<R>(P->geo, t, P->cb, (const cplx<R>*)cot, hx, st);
+  if (e == hipSuccess)
+    e = tffr::launch_adj_rows<R>(P->geo, t, sample_type(P), hx, smp, (const R*)ph, (const R*)da, w, (cplx<R>*)gs,
+                                 (R*)gph, (R*)gda, st);
+  return hip_status(e);
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+void tffr_default_params(tffr_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->weighting = TFFR_W_TFFR;
+  p->window_a = 0.01;
+  p->q = 3.0;
+  p->band_r = 2;
+  p->tau = 0.97;
+  p->thresh_mode = TFFR_THRESH_LITERAL;
+  p->kernel_width = 7;
+  p->upsampfac = 2.0;
+  p->dtype = TFFR_C64;
+}
+
+const char* tffr_status_string(tffr_status s) {
+  switch (s) {
+    case TFFR_OK: return "TFFR_OK";
+    case TFFR_ERR_ARG: return "TFFR_ERR_ARG: invalid argument";
+    case TFFR_ERR_EVANESCENT: return "TFFR_ERR_EVANESCENT: 4 k^2 <= ku^2 for some sample";
+    case TFFR_ERR_NONMONOTONE: return "TFFR_ERR_NONMONOTONE: k is not strictly increasing";
+    case TFFR_ERR_LAYOUT: return "TFFR_ERR_LAYOUT: buffer layout or size mismatch";
+    case TFFR_ERR_UNSUPPORTED: return "TFFR_ERR_UNSUPPORTED: configuration not supported";
+    case TFFR_ERR_SINGULAR: return "TFFR_ERR_SINGULAR: plain-FFR frame product is singular";
+    case TFFR_ERR_NOMEM: return "TFFR_ERR_NOMEM: allocation failed";
+    case TFFR_ERR_HIP: return "TFFR_ERR_HIP: HIP runtime error";
+  }
+  return "TFFR_ERR_UNKNOWN";
+}
+
+tffr_status tffr_validate(const tffr_params* p, const double* k, const double* ku) {
+  tffr_status s = check_params(p);
+  if (s != TFFR_OK) return s;
+  if (!k || !ku) return TFFR_ERR_ARG;
+  for (int i = 0; i < p->n_freq; ++i)
+    if (!std::isfinite(k[i])) return TFFR_ERR_ARG;
+  for (int i = 0; i < p->n_pulses; ++i)
+    if (!std::isfinite(ku[i])) return TFFR_ERR_ARG;
+  for (int i = 1; i < p->n_freq; ++i)
+    if (!(k[i] > k[i - 1])) return TFFR_ERR_NONMONOTONE;
+  double kmin = std::fabs(k[0]), kumax = 0.0;
+  for (int i = 0; i < p->n_freq; ++i) kmin = std::min(kmin, std::fabs(k[i]));
+  for (int i = 0; i < p->n_pulses; ++i) kumax = std::max(kumax, std::fabs(ku[i]));
+  if (!(4.0 * (kmin * kmin) - kumax * kumax > 0.0)) return TFFR_ERR_EVANESCENT;
+  if (p->weighting == TFFR_W_FFR && ffr_halfband(p, k, ku) > kMaxHalfBand) return TFFR_ERR_UNSUPPORTED;
+  return TFFR_OK;
+}
+
+tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double* ku, tffr_plan** out) {
+  if (!out) return TFFR_ERR_ARG;
+  *out = nullptr;
+  tffr_status s = tffr_validate(p, k, ku);
+  if (s != TFFR_OK) return s;
+  tffr_plan* P = new (std::nothrow) tffr_plan();
+  if (!P) return TFFR_ERR_NOMEM;
+  P->prm = *p;
+  auto fail = [&](tffr_status e) {
+    delete P;
+    return e;
+  };
+  if (hipGetDevice(&P->device) != hipSuccess) return fail(TFFR_ERR_HIP);
+
+  const int W = p->kernel_width;
+  const int lognx = std::max(6, log2_pow2_at_least(p->upsampfac * p->mx));
+  const int logny = std::max(6, log2_pow2_at_least(p->upsampfac * p->my));
+  const int nfx = 1 << lognx, nfy = 1 << logny;
+  // ES shape for the achieved upsampling factor: beta = 2.30 W at sigma = 2, scaled
+  // for other sigma with the usual (1 - 1/(2 sigma)) law.
+  const double sig = std::min((double)nfx / p->mx, (double)nfy / p->my);
+  P->beta = 2.30 * W * (1.0 - 1.0 / (2.0 * sig)) / 0.75;
+  const size_t csz = P->csize();
+  const size_t lds_max = tffr::max_dynamic_lds();
+  if (((size_t)nfx * csz) + (p->weighting == TFFR_W_FFR ? (size_t)p->n_freq * csz : 0) > lds_max ||
+      (size_t)nfy * csz > lds_max)
+    return fail(TFFR_ERR_UNSUPPORTED);
+  // range columns per workgroup in the azimuth stage: fill <= 64 KB of LDS but keep
+  // at least ~512 workgroups in flight
+  int cb = (int)std::max<size_t>(1, std::min<size_t>(8, 65536 / ((size_t)nfy * csz)));
+  while (cb > 1 && (p->mx + cb - 1) / cb < 512) cb >>= 1;
+  if (const char* e = std::getenv("TFFR_AZ_COLS")) {
+    const int v = std::atoi(e);
+    if (v >= 1 && v <= 16 && (size_t)v * nfy * csz <= lds_max) cb = v;
+  }
+  P->cb = cb;
+
+  tffr::Geo& g = P->geo;
+  g.n_pulses = p->n_pulses;
+  g.n_freq = p->n_freq;
+  g.mx = p->mx;
+  g.my = p->my;
+  g.nfx = nfx;
+  g.nfy = nfy;
+  g.lognfx = lognx;
+  g.lognfy = logny;
+  g.W = W;
+  g.weighting = p->weighting;
+  g.thresh_mode = p->thresh_mode;
+  g.band_r = p->band_r;
+  g.beta = P->beta;
+  g.tx_scale = p->fov_x / (2.0 * kPi * p->mx);
+  g.fov_x = p->fov_x;
+  g.a = p->window_a;
+  g.q = p->q;
+  g.tau = p->tau;
+  g.ema2 = std::exp(-p->window_a / 2.0);
+  g.epa2 = std::exp(p->window_a / 2.0);
+  const double g0 = frame_diag(0.0, p->window_a, p->q);
+  g.inv_g0 = g0 != 0.0 ? 1.0 / g0 : 0.0;
+  g.keep0 = p->thresh_mode == TFFR_THRESH_LITERAL ? (std::fabs(g.inv_g0) >= p->tau) : (g0 >= p->tau);
+  g.near_rel = 1e-5;
+
+  std::vector<double> kv(k, k + p->n_freq), kuv(ku, ku + p->n_pulses);
+  // per-slice azimuth taps
+  std::vector<int32_t> ys(p->n_pulses);
+  std::vector<double> taps((size_t)p->n_pulses * W);
+  for (int n = 0; n < p->n_pulses; ++n) {
+    const double t = ku[n] * p->fov_y / (2.0 * kPi * p->my);
+    const double u = (t - std::floor(t)) * nfy;
+    const double ui = std::floor(u), f = u - ui;
+    const int k0 = (int)std::ceil(f - W / 2.0);
+    ys[n] = (int32_t)ui + k0;
+    for (int i = 0; i < W; ++i) taps[(size_t)n * W + i] = es((k0 + i - f) / (W / 2.0), P->beta);
+  }
+  std::vector<double> dx = deapod_table(p->mx, nfx, W, P->beta), dy = deapod_table(p->my, nfy, W, P->beta);
+  auto twiddles = [](int n) {
+    std::vector<double> tw(2 * (size_t)n);
+    for (int m = 0; m < n; ++m) {
+      tw[2 * m] = std::cos(2.0 * kPi * ((double)m / n));
+      tw[2 * m + 1] = std::sin(2.0 * kPi * ((double)m / n));
+    }
+    return tw;
+  };
+  std::vector<double> twx = twiddles(nfx), twy = twiddles(nfy);
+  if (P->dbl()) {
+    s = upload(P->ky, kuv);
+    if (s == TFFR_OK) s = upload(P->ytap, taps);
+    if (s == TFFR_OK) s = upload(P->deapx, dx);
+    if (s == TFFR_OK) s = upload(P->deapy, dy);
+    if (s == TFFR_OK) s = upload(P->twx, twx);
+    if (s == TFFR_OK) s = upload(P->twy, twy);
+  } else {
+    s = upload(P->ky, cast<float>(kuv));
+    if (s == TFFR_OK) s = upload(P->ytap, cast<float>(taps));
+    if (s == TFFR_OK) s = upload(P->deapx, cast<float>(dx));
+    if (s == TFFR_OK) s = upload(P->deapy, cast<float>(dy));
+    if (s == TFFR_OK) s = upload(P->twx, cast<float>(twx));
+    if (s == TFFR_OK) s = upload(P->twy, cast<float>(twy));
+  }
+  if (s == TFFR_OK) s = upload(P->k, kv);
+  if (s == TFFR_OK) s = upload(P->ku, kuv);
+  if (s == TFFR_OK) s = upload(P->ystart, ys);
+  if (s != TFFR_OK) return fail(s);
+
+  // tFFR weight polynomial (float path, integer q only: the tap set is then constant on (0, 1))
+  g.use_poly = 0;
+  g.nseg = 32;
+  g.deg = 7;
+  if (!P->dbl() && p->weighting == TFFR_W_TFFR && std::fabs(p->q - std::round(p->q)) < 1e-12) {
+    std::vector<float> poly;
+    if (fit_weight_poly(p->window_a, p->q, g.nseg, g.deg, poly)) {
+      s = upload(P->poly, poly);
+      if (s != TFFR_OK) return fail(s);
+      g.use_poly = 1;
+    }
+  }
+
+  // workspace layout
+  size_t off = 0;
+  P->off_hx = off;
+  off = align_up(off + (size_t)p->n_pulses * p->mx * csz);
+  P->off_part = off;
+  off = align_up(off + sizeof(double) * 2 * kPartials);
+  P->off_kept = off;
+  off = align_up(off + sizeof(unsigned long long) * kPartials);
+  P->off_count = off;
+  off = align_up(off + sizeof(long long));
+  P->off_status = off;
+  off = align_up(off + sizeof(int));
+  if (p->weighting == TFFR_W_FFR) {
+    P->ffr_halfband = ffr_halfband(p, k, ku);
+    g.band_b = P->ffr_halfband;
+    const size_t band = (size_t)p->n_pulses * p->n_freq * (2 * g.band_b + 1) * sizeof(double);
+    P->off_gband = off;
+    off = align_up(off + band);
+    P->off_zband = off;
+    off = align_up(off + band);
+  }
+  P->work_bytes = off;
+
+  // plain FFR: solve once per geometry, keep D, report a singular frame product
+  if (p->weighting == TFFR_W_FFR) {
+    const size_t dbytes = (size_t)p->n_pulses * p->n_freq * (2 * p->band_r + 1) * P->rsize();
+    void* work = nullptr;
+    if (hipMalloc(&P->ffr_d.p, dbytes) != hipSuccess) return fail(TFFR_ERR_NOMEM);
+    if (hipMalloc(&work, P->work_bytes) != hipSuccess) return fail(TFFR_ERR_NOMEM);
+    char* wb = (char*)work;
+    hipError_t e = hipMemset(wb + P->off_status, 0, sizeof(int));
+    if (e == hipSuccess) {
+      if (P->dbl())
+        e = tffr::launch_ffr<double>(g, tables<double>(P), (double*)(wb + P->off_gband), (double*)(wb + P->off_zband),
+                                     (double*)P->ffr_d.p, (int*)(wb + P->off_status), 0);
+      else
+        e = tffr::launch_ffr<float>(g, tables<float>(P), (double*)(wb + P->off_gband), (double*)(wb + P->off_zband),
+                                    (float*)P->ffr_d.p, (int*)(wb + P->off_status), 0);
+    }
+    int st = 0;
+    if (e == hipSuccess) e = hipMemcpy(&st, wb + P->off_status, sizeof(int), hipMemcpyDeviceToHost);
+    (void)hipFree(work);
+    if (e != hipSuccess) return fail(TFFR_ERR_HIP);
+    if (st != 0) return fail(TFFR_ERR_SINGULAR);
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return fail(TFFR_ERR_HIP);
+  *out = P;
+  return TFFR_OK;
+}
+
+void tffr_plan_destroy(tffr_plan* plan) { delete plan; }
+
+size_t tffr_workspace_bytes(const tffr_plan* plan) { return plan ? plan->work_bytes : 0; }
+
+tffr_status tffr_plan_info(const tffr_plan* plan, int32_t* nfx, int32_t* nfy, double* beta, int32_t* hb) {
+  if (!plan) return TFFR_ERR_ARG;
+  if (nfx) *nfx = plan->geo.nfx;
+  if (nfy) *nfy = plan->geo.nfy;
+  if (beta) *beta = plan->beta;
+  if (hb) *hb = plan->ffr_halfband;
+  return TFFR_OK;
+}
+
+
+tffr_status tffr_forward(tffr_plan* P, const void* smp, const void* ph, const void* da, const void* uw, void* img,
+                         void* work, tffr_stream stream) {
+  if (!P || !smp || !img || !work) return TFFR_ERR_ARG;
+  if (P->prm.weighting == TFFR_W_USER && !uw) return TFFR_ERR_ARG;
+  if (!aligned(work, 16) || !aligned(img, P->csize() / 2) || !aligned(smp, 4)) return TFFR_ERR_LAYOUT;
+  hipStream_t st = (hipStream_t)stream;
+  return P->dbl() ? do_forward<double>(P, smp, ph, da, uw, img, work, st, -1)
+                  : do_forward<float>(P, smp, ph, da, uw, img, work, st, -1);
+}
+
+tffr_status tffr_adjoint(tffr_plan* P, const void* cot, const void* smp, const void* ph, const void* da, const void* uw,
+                         void* gs, void* gph, void* gda, void* work, tffr_stream stream) {
+  if (!P || !cot || !gs || !work) return TFFR_ERR_ARG;
+  if ((gph || gda) && !smp) return TFFR_ERR_ARG;
+  if (P->prm.weighting == TFFR_W_USER && !uw) return TFFR_ERR_ARG;
+  if (!aligned(work, 16) || !aligned(cot, P->csize() / 2) || !aligned(gs, P->csize() / 2)) return TFFR_ERR_LAYOUT;
+  hipStream_t st = (hipStream_t)stream;
+  return P->dbl() ? do_adjoint<double>(P, cot, smp, ph, da, uw, gs, gph, gda, work, st)
+                  : do_adjoint<float>(P, cot, smp, ph, da, uw, gs, gph, gda, work, st);
+}
+
+tffr_status tffr_entropy(tffr_plan* P, const void* img, double* loss, void* grad, void* work, tffr_stream stream) {
+  if (!P || !img || !loss || !work) return TFFR_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  double* part = (double*)((char*)work + P->off_part);
+  const size_t count = (size_t)P->prm.mx * P->prm.my;
+  const int nparts = (int)std::max<size_t>(1, std::min<size_t>(kPartials, (count + 1023) / 1024));
+  hipError_t e = P->dbl() ? tffr::launch_entropy<double>(P->geo, (const cplx<double>*)img, part, nparts, loss,
+                                                         (cplx<double>*)grad, st)
+                          : tffr::launch_entropy<float>(P->geo, (const cplx<float>*)img, part, nparts, loss,
+                                                        (cplx<float>*)grad, st);
+  return hip_status(e);
+}
+
+tffr_status tffr_weights(tffr_plan* P, void* d_w, void* work, tffr_stream stream) {
+  if (!P || !d_w || !work) return TFFR_ERR_ARG;
+  if (P->prm.weighting == TFFR_W_USER) return TFFR_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  char* wb = (char*)work;
+  hipError_t e;
+  if (P->prm.weighting == TFFR_W_FFR) {
+    int* status = (int*)(wb + P->off_status);
+    e = P->dbl() ? tffr::launch_ffr<double>(P->geo, tables<double>(P), (double*)(wb + P->off_gband),
+                                            (double*)(wb + P->off_zband), (double*)d_w, status, st)
+                 : tffr::launch_ffr<float>(P->geo, tables<float>(P), (double*)(wb + P->off_gband),
+                                           (double*)(wb + P->off_zband), (float*)d_w, status, st);
+  } else {
+    unsigned long long* kept = (unsigned long long*)(wb + P->off_kept);
+    e = P->dbl() ? tffr::launch_weights<double>(P->geo, tables<double>(P), (double*)d_w, kept, kPartials, st)
+                 : tffr::launch_weights<float>(P->geo, tables<float>(P), (float*)d_w, kept, kPartials, st);
+  }
+  return hip_status(e);
+}
+
+tffr_status tffr_kept_count(tffr_plan* P, void* work, int64_t* count, tffr_stream stream) {
+  if (!P || !work || !count) return TFFR_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  char* wb = (char*)work;
+  unsigned long long* kept = (unsigned long long*)(wb + P->off_kept);
+  long long* dcount = (long long*)(wb + P->off_count);
+  hipError_t e = P->dbl() ? tffr::launch_weights<double>(P->geo, tables<double>(P), nullptr, kept, kPartials, st)
+                          : tffr::launch_weights<float>(P->geo, tables<float>(P), nullptr, kept, kPartials, st);
+  if (e == hipSuccess) e = tffr::launch_sum_u64(kept, kPartials, dcount, st);
+  long long h = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, dcount, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return TFFR_ERR_HIP;
+  *count = (int64_t)h;
+  return TFFR_OK;
+}
+
+tffr_status tffr_debug_fft(int32_t log2n, int32_t batch, int32_t sign, int32_t dtype, const void* in, void* out,
+                           tffr_stream stream) {
+  if (log2n < 6 || log2n > kMaxLogN || batch < 1 || (sign != 1 && sign != -1) || !in || !out) return TFFR_ERR_ARG;
+  if (dtype != TFFR_C64 && dtype != TFFR_C128) return TFFR_ERR_UNSUPPORTED;
+  const size_t csz = dtype == TFFR_C128 ? 16 : 8;
+  if (((size_t)csz << log2n) > tffr::max_dynamic_lds()) return TFFR_ERR_UNSUPPORTED;
+  const int n = 1 << log2n;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<double> tw(2 * (size_t)n);
+  for (int m = 0; m < n; ++m) {
+    tw[2 * m] = std::cos(2.0 * kPi * ((double)m / n));
+    tw[2 * m + 1] = std::sin(2.0 * kPi * ((double)m / n));
+  }
+  DevBuf dtw;
+  tffr_status s = dtype == TFFR_C128 ? upload(dtw, tw) : upload(dtw, cast<float>(tw));
+  if (s != TFFR_OK) return s;
+  hipError_t e = dtype == TFFR_C128
+                     ? tffr::launch_fft<double>(log2n, batch, sign, (const cplx<double>*)in, (cplx<double>*)out,
+                                                (const cplx<double>*)dtw.p, st)
+                     : tffr::launch_fft<float>(log2n, batch, sign, (const cplx<float>*)in, (cplx<float>*)out,
+                                               (const cplx<float>*)dtw.p, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);  // the twiddle table is freed on return
+  return hip_status(e);
+}
+
+tffr_status tffr_debug_rows(tffr_plan* P, int32_t stage, const void* smp, const void* ph, const void* da,
+                            const void* uw, void* out, tffr_stream stream) {
+  if (!P || !smp || !out || (stage != 0 && stage != 1)) return TFFR_ERR_ARG;
+  if (P->prm.weighting == TFFR_W_USER && !uw) return TFFR_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  return P->dbl() ? do_forward<double>(P, smp, ph, da, uw, out, nullptr, st, stage)
+                  : do_forward<float>(P, smp, ph, da, uw, out, nullptr, st, stage);
+}
+
+}  // extern "C"

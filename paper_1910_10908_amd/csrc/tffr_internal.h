@@ -1,0 +1,85 @@
+// Internal types shared by the host plan (tffr_host.hip) and the kernels
+// (tffr_kernels.hip).  Nothing here crosses the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace tffr {
+
+template <typename R>
+struct cplx {
+  R x, y;
+};
+
+struct half2s {  // two IEEE binary16 values (re, im)
+  _Float16 x, y;
+};
+
+// Scalar geometry and method constants, passed by value to every kernel.
+struct Geo {
+  int32_t n_pulses, n_freq, mx, my;
+  int32_t nfx, nfy, lognfx, lognfy;  // fine grid sizes (powers of two)
+  int32_t W;                         // gridding kernel width (taps)
+  int32_t weighting, thresh_mode, band_r, band_b;
+  int32_t use_poly, nseg, deg;  // tFFR weight polynomial (float path)
+  int32_t keep0;                // threshold decision for a sample exactly on the lattice
+  double beta;                  // ES kernel shape
+  double tx_scale;              // kx -> cycles per range pixel: fov_x / (2 pi mx)
+  double fov_x;                 // kx -> lattice coordinate: kx * fov_x / (2 pi)
+  double a, q, tau;
+  double ema2, epa2;  // exp(-a/2), exp(+a/2)
+  double inv_g0;      // 1/g(0) for a sample exactly on the lattice
+  double near_rel;    // polynomial weights this close to the threshold are re-decided in FP64
+};
+
+// Small device tables owned by the plan, in the compute type R.
+template <typename R>
+struct Tab {
+  const double* k;        // [n_freq]   fast-time wavenumbers
+  const double* ku;       // [n_pulses] azimuth wavenumbers
+  const R* ky;            // [n_pulses] ky = ku in the compute type (row phase)
+  const int32_t* ystart;  // [n_pulses] first azimuth fine cell of the slice's taps
+  const R* ytap;          // [n_pulses][W] azimuth kernel taps of the slice
+  const R* deapx;         // [mx] 1 / kernel transform, range
+  const R* deapy;         // [my] 1 / kernel transform, azimuth
+  const cplx<R>* twx;     // [nfx] exp(+2 pi i m / nfx)
+  const cplx<R>* twy;     // [nfy] exp(+2 pi i m / nfy)
+  const float* poly;      // [nseg][deg+1] tFFR weight polynomial (float path), or null
+};
+
+enum SampleType { ST_C64 = 0, ST_C128 = 1, ST_H2 = 2 };
+
+// Launchers (tffr_kernels.hip).  All enqueue on `st` and return the launch status.
+template <typename R>
+hipError_t launch_fwd_rows(const Geo& g, const Tab<R>& t, int stype, const void* samples,
+                           const R* phase, const R* dalong, const R* w, cplx<R>* out,
+                           int stage, hipStream_t st);
+template <typename R>
+hipError_t launch_fwd_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>* hx,
+                           cplx<R>* img, hipStream_t st);
+template <typename R>
+hipError_t launch_adj_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>* cot,
+                           cplx<R>* hx, hipStream_t st);
+template <typename R>
+hipError_t launch_adj_rows(const Geo& g, const Tab<R>& t, int stype, const cplx<R>* hx,
+                           const void* samples, const R* phase, const R* dalong, const R* w,
+                           cplx<R>* grad_s, R* grad_phase, R* grad_dalong, hipStream_t st);
+template <typename R>
+hipError_t launch_weights(const Geo& g, const Tab<R>& t, R* w, unsigned long long* kept_partial,
+                          int nblocks, hipStream_t st);
+hipError_t launch_sum_u64(const unsigned long long* parts, int n, long long* out, hipStream_t st);
+template <typename R>
+hipError_t launch_ffr(const Geo& g, const Tab<R>& t, double* gband, double* zband, R* dband,
+                      int* status, hipStream_t st);
+template <typename R>
+hipError_t launch_entropy(const Geo& g, const cplx<R>* img, double* partials, int nparts,
+                          double* loss, cplx<R>* grad, hipStream_t st);
+template <typename R>
+hipError_t launch_fft(int log2n, int batch, int sign, const cplx<R>* in, cplx<R>* out,
+                      const cplx<R>* tw, hipStream_t st);
+
+size_t max_dynamic_lds();  // bytes of LDS one workgroup may use on this device
+
+}  // namespace tffr

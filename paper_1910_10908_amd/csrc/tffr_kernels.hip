@@ -1,0 +1,861 @@
+// HIP kernels of libtffr for gfx950 (CDNA4).
+//
+// The image I[jx,jy] = sum_{n,p} c[n,p] exp(i (kx[n,p] X[jx] + ky[n] Y[jy])) separates
+// along the slice structure of stripmap data (each azimuth slice n has one ky, its
+// samples are non-uniform in kx only; Sec. II-A and Algorithm 1):
+//
+//   range stage    Hx[n][jx] = sum_p c[n,p] exp(i kx[n,p] X[jx])         one slice per workgroup
+//   azimuth stage  I[jx][jy] = sum_n Hx[n][jx] exp(i ky[n] Y[jy])        CB range columns per workgroup
+//
+// Each stage is a 1-D type-1 NUFFT done entirely in LDS: spread with an
+// exponential-of-semicircle (ES) kernel onto an oversampled periodic grid, Stockham
+// radix-8 FFT, keep the centred bins and divide by the kernel's transform.  The
+// adjoint runs the two type-2 stages in reverse.  Samples are read once, each
+// intermediate is written once and read once, and nothing is done with global atomics.
+//
+// Coordinates are reduced in FP64 (kx up to ~430 rad/m times pixel sizes makes
+// phases of ~1e4 rad) and kept as an (integer cell, FP32 fraction) pair.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "tffr_internal.h"
+
+namespace tffr {
+
+#define TFFR_PI 3.141592653589793
+
+// ----------------------------------------------------------------------------- complex
+template <typename R>
+__device__ __forceinline__ cplx<R> operator+(cplx<R> a, cplx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ cplx<R> operator-(cplx<R> a, cplx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ cplx<R> operator*(R s, cplx<R> a) { return {s * a.x, s * a.y}; }
+template <typename R>
+__device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename R>
+__device__ __forceinline__ cplx<R> cmulc(cplx<R> a, cplx<R> b) {  // a * conj(b)
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <int SIGN, typename R>
+__device__ __forceinline__ cplx<R> mul_si(cplx<R> a) {  // a * (SIGN i)
+  return SIGN > 0 ? cplx<R>{-a.y, a.x} : cplx<R>{a.y, -a.x};
+}
+
+template <typename R>
+__device__ __forceinline__ void lds_add(cplx<R>* p, cplx<R> v) {
+  atomicAdd(&p->x, v.x);
+  atomicAdd(&p->y, v.y);
+}
+
+// ----------------------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int NT>
+__device__ double block_sum(double v) {
+  __shared__ double red[NT / 64];
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) t += red[i];
+  return t;
+}
+
+// ----------------------------------------------------------------------------- LDS FFT
+// Small DFTs in registers: X[k] = sum_r x[r] exp(SIGN 2 pi i r k / R).
+template <int SIGN, typename R>
+__device__ __forceinline__ void dft2(cplx<R>* a) {
+  cplx<R> t = a[0];
+  a[0] = t + a[1];
+  a[1] = t - a[1];
+}
+template <int SIGN, typename R>
+__device__ __forceinline__ void dft4(cplx<R>* a) {
+  cplx<R> s0 = a[0] + a[2], d0 = a[0] - a[2];
+  cplx<R> s1 = a[1] + a[3], d1 = mul_si<SIGN>(a[1] - a[3]);
+  a[0] = s0 + s1;
+  a[2] = s0 - s1;
+  a[1] = d0 + d1;
+  a[3] = d0 - d1;
+}
+template <int SIGN, typename R>
+__device__ __forceinline__ void dft8(cplx<R>* a) {
+  cplx<R> e[4] = {a[0], a[2], a[4], a[6]};
+  cplx<R> o[4] = {a[1], a[3], a[5], a[7]};
+  dft4<SIGN>(e);
+  dft4<SIGN>(o);
+  const R h = R(0.70710678118654752440);
+  // twiddles exp(SIGN 2 pi i k / 8): (1 + SIGN i)/sqrt2, SIGN i, (-1 + SIGN i)/sqrt2
+  cplx<R> o1 = {h * (o[1].x - R(SIGN) * o[1].y), h * (o[1].y + R(SIGN) * o[1].x)};
+  cplx<R> o2 = mul_si<SIGN>(o[2]);
+  cplx<R> o3 = {h * (-o[3].x - R(SIGN) * o[3].y), h * (-o[3].y + R(SIGN) * o[3].x)};
+  a[0] = e[0] + o[0];
+  a[4] = e[0] - o[0];
+  a[1] = e[1] + o1;
+  a[5] = e[1] - o1;
+  a[2] = e[2] + o2;
+  a[6] = e[2] - o2;
+  a[3] = e[3] + o3;
+  a[7] = e[3] - o3;
+}
+template <int SIGN, int RAD, typename R>
+__device__ __forceinline__ void dft(cplx<R>* a) {
+  if constexpr (RAD == 8) dft8<SIGN>(a);
+  else if constexpr (RAD == 4) dft4<SIGN>(a);
+  else dft2<SIGN>(a);
+}
+
+// One Stockham autosort stage of radix RAD after spans P (in place: all reads, barrier,
+// all writes, barrier).  Butterfly i reads x[i + r N/RAD], applies the twiddles
+// exp(SIGN 2 pi i r k / (P RAD)) with k = i mod P, and writes y[(i - k) RAD + k + r P].
+template <int SIGN, int N, int RAD, int P, int NT, typename R>
+__device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* __restrict__ tw) {
+  constexpr int NB = N / RAD;
+  constexpr int BPT = (NB + NT - 1) / NT;
+  cplx<R> v[BPT][RAD];
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    const int i = threadIdx.x + b * NT;
+    if (NB % NT == 0 || i < NB) {
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[b][r] = buf[i + r * NB];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    const int i = threadIdx.x + b * NT;
+    if (NB % NT == 0 || i < NB) {
+      const int k = i & (P - 1);
+      if constexpr (P > 1) {
+        constexpr int STEP = N / (P * RAD);
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) {
+          cplx<R> w = tw[r * k * STEP];
+          if (SIGN < 0) w.y = -w.y;
+          v[b][r] = cmul(v[b][r], w);
+        }
+      }
+      dft<SIGN, RAD>(v[b]);
+      const int j = (i - k) * RAD + k;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) buf[j + r * P] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int SIGN, int N, int P, int NT, typename R>
+__device__ __forceinline__ void fft_from(cplx<R>* buf, const cplx<R>* __restrict__ tw) {
+  if constexpr (P < N) {
+    constexpr int RAD = (N / P) >= 8 ? 8 : (N / P);
+    fft_stage<SIGN, N, RAD, P, NT>(buf, tw);
+    fft_from<SIGN, N, P * RAD, NT>(buf, tw);
+  }
+}
+
+// out[j] = sum_g buf[g] exp(SIGN 2 pi i g j / N), in place in LDS, natural order.
+// Call with all NT threads; the caller must barrier before (writes to buf are read).
+template <int SIGN, int N, int NT, typename R>
+__device__ __forceinline__ void lds_fft(cplx<R>* buf, const cplx<R>* __restrict__ tw) {
+  fft_from<SIGN, N, 1, NT>(buf, tw);
+}
+
+// ----------------------------------------------------------------------------- geometry
+// Stolt map and lattice coordinate, rounded exactly as written (no contraction), so a
+// threshold decision taken from them matches an FP64 evaluation in the same order.
+__device__ __forceinline__ double stolt_kx(double k, double ku) {
+#pragma clang fp contract(off)
+  return sqrt(4.0 * (k * k) - ku * ku);
+}
+__device__ __forceinline__ double lattice_coord(double kx, double fov) {
+#pragma clang fp contract(off)
+  return kx * fov / (2.0 * TFFR_PI);
+}
+
+// Finite-interval cosine transforms of w = exp(-a|t|) and 1/w over [-1/2, 1/2]
+// (the entries of W and Psi on the image's own lattice).
+__device__ __forceinline__ double r_w(double d, const Geo& g) {
+  const double b = 2.0 * TFFR_PI * d;
+  double sn, cs;
+  sincos(b / 2.0, &sn, &cs);
+  const double den = g.a * g.a + b * b;
+  if (den == 0.0) return 1.0;
+  return 2.0 * (g.a + g.ema2 * (b * sn - g.a * cs)) / den;
+}
+__device__ __forceinline__ double r_psi(double d, const Geo& g) {
+  const double b = 2.0 * TFFR_PI * d;
+  double sn, cs;
+  sincos(b / 2.0, &sn, &cs);
+  const double den = g.a * g.a + b * b;
+  if (den == 0.0) return 1.0;
+  return 2.0 * (g.epa2 * (b * sn + g.a * cs) - g.a) / den;
+}
+
+// g(delta) = sum_{|k - delta| < q} R_Psi(k - delta) R_W(k - delta): the diagonal of the
+// truncated frame product for a sample at fractional lattice offset delta.
+__device__ double frame_diag(const Geo& g, double delta) {
+  const int K = (int)ceil(g.q) + 1;
+  double acc = 0.0;
+  for (int k = -K; k <= K; ++k) {
+    const double d = (double)k - delta;
+    if (fabs(d) < g.q) acc += r_psi(d, g) * r_w(d, g);
+  }
+  return acc;
+}
+
+// tFFR weight R_tau(1/g) of a sample at lattice coordinate lam.
+template <typename R>
+__device__ __forceinline__ R tffr_weight(const Geo& g, const float* __restrict__ poly, double lam) {
+  const double delta = lam - floor(lam);
+  if (delta == 0.0) return g.keep0 ? (R)g.inv_g0 : (R)0;
+  if (sizeof(R) == 4 && g.use_poly) {
+    const double xs = delta * g.nseg;
+    const int seg = min((int)xs, g.nseg - 1);
+    const float t = (float)(2.0 * (xs - seg) - 1.0);
+    const float* c = poly + seg * (g.deg + 1);
+    float v = c[0];
+    for (int i = 1; i <= g.deg; ++i) v = fmaf(v, t, c[i]);
+    const float thr = g.thresh_mode == 0 ? (float)g.tau : (float)(1.0 / g.tau);
+    if (fabsf(v - thr) > (float)g.near_rel * thr) {
+      const bool keep = g.thresh_mode == 0 ? (v >= thr) : (v <= thr);
+      return keep ? (R)v : (R)0;
+    }
+  }
+  const double gd = frame_diag(g, delta);
+  const double inv = gd != 0.0 ? 1.0 / gd : 0.0;
+  const bool keep = g.thresh_mode == 0 ? (fabs(inv) >= g.tau) : (gd >= g.tau);
+  return keep ? (R)inv : (R)0;
+}
+
+// Weight of sample (n, p) for the diagonal methods.
+template <typename R>
+__device__ __forceinline__ R diag_weight(const Geo& g, const Tab<R>& t, double ku, int p, double lam) {
+  switch (g.weighting) {
+    case 3:  // tFFR
+      return tffr_weight<R>(g, t.poly, lam);
+    case 1: {  // trapezoid quadrature in lam along the slice
+      if (g.n_freq == 1) return (R)1;
+      const int plo = p > 0 ? p - 1 : 0, phi = p < g.n_freq - 1 ? p + 1 : g.n_freq - 1;
+      const double llo = lattice_coord(stolt_kx(t.k[plo], ku), g.fov_x);
+      const double lhi = lattice_coord(stolt_kx(t.k[phi], ku), g.fov_x);
+      return (R)((lhi - llo) / 2.0);
+    }
+    default:
+      return (R)1;
+  }
+}
+
+// ES kernel exp(beta (sqrt(1 - z^2) - 1)), zero for |z| >= 1.
+__device__ __forceinline__ float es_kernel(float z, float beta) {
+  const float s = 1.0f - z * z;
+  return s > 0.0f ? __expf(beta * (__fsqrt_rn(s) - 1.0f)) : 0.0f;
+}
+__device__ __forceinline__ double es_kernel(double z, double beta) {
+  const double s = 1.0 - z * z;
+  return s > 0.0 ? exp(beta * (sqrt(s) - 1.0)) : 0.0;
+}
+
+// Fine-grid position of a sample with lattice-per-pixel coordinate t (cycles per pixel):
+// u = frac(t) n in [0, n), split in FP64 into an integer cell and a fraction.
+template <typename R>
+__device__ __forceinline__ void fine_pos(double t, int n, int& ui, R& f) {
+  const double u = (t - floor(t)) * (double)n;
+  const double fu = floor(u);
+  ui = (int)fu;
+  f = (R)(u - fu);
+}
+
+template <typename R>
+__device__ __forceinline__ cplx<R> load_sample(const void* s, int stype, size_t i) {
+  if (stype == ST_H2) {
+    const half2s h = ((const half2s*)s)[i];
+    return {(R)(float)h.x, (R)(float)h.y};
+  }
+  if (stype == ST_C128) {
+    const cplx<double> v = ((const cplx<double>*)s)[i];
+    return {(R)v.x, (R)v.y};
+  }
+  const cplx<float> v = ((const cplx<float>*)s)[i];
+  return {(R)v.x, (R)v.y};
+}
+
+template <typename R>
+__device__ __forceinline__ cplx<R> row_rotation(const Tab<R>& t, const R* phase, const R* dalong, int n) {
+  R psi = 0;
+  if (phase) psi += phase[n];
+  if (dalong) psi += t.ky[n] * dalong[n];
+  R sn, cs;
+  if constexpr (sizeof(R) == 4) sincosf(psi, &sn, &cs);
+  else sincos(psi, &sn, &cs);
+  return {cs, sn};
+}
+
+// Weighted, phased sample c[n,p] (forward input of the gridding).
+template <typename R>
+__device__ __forceinline__ cplx<R> weighted_sample(const Geo& g, const Tab<R>& t, int stype,
+                                                   const void* samples, const R* w, int n, int p,
+                                                   double ku, double lam, cplx<R> rot) {
+  const size_t base = (size_t)n * g.n_freq;
+  if (g.weighting == 2) {  // plain FFR: banded D within the slice
+    const int r = g.band_r;
+    const R* drow = w + (base + p) * (2 * r + 1);
+    cplx<R> acc = {0, 0};
+    for (int o = -r; o <= r; ++o) {
+      const int pp = p + o;
+      if (pp >= 0 && pp < g.n_freq) acc = acc + drow[r + o] * load_sample<R>(samples, stype, base + pp);
+    }
+    return cmul(rot, acc);
+  }
+  const R wt = w ? w[base + p] : diag_weight<R>(g, t, ku, p, lam);
+  return wt * cmul(rot, load_sample<R>(samples, stype, base + p));
+}
+
+// ============================================================================ forward
+// Range stage: one azimuth slice per workgroup.  Spread the slice's weighted samples
+// onto the periodic fine row (LDS atomics), inverse FFT, keep the centred mx bins and
+// divide by the kernel transform.  stage 0 dumps the gridded row instead.
+template <typename R, int LOGN, int NT>
+__global__ __launch_bounds__(NT) void k_fwd_rows(Geo g, Tab<R> t, int stype, const void* __restrict__ samples,
+                                                 const R* __restrict__ phase, const R* __restrict__ dalong,
+                                                 const R* __restrict__ w, cplx<R>* __restrict__ out, int stage) {
+  constexpr int N = 1 << LOGN;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem);
+  const int n = blockIdx.x;
+  for (int i = threadIdx.x; i < N; i += NT) buf[i] = {0, 0};
+  const cplx<R> rot = row_rotation(t, phase, dalong, n);
+  const double ku = t.ku[n];
+  const R halfw = (R)(0.5 * g.W), inv_halfw = (R)(2.0 / g.W), beta = (R)g.beta;
+  __syncthreads();
+  for (int p = threadIdx.x; p < g.n_freq; p += NT) {
+    const double kx = stolt_kx(t.k[p], ku);
+    const double lam = lattice_coord(kx, g.fov_x);
+    const cplx<R> c = weighted_sample<R>(g, t, stype, samples, w, n, p, ku, lam, rot);
+    int ui;
+    R f;
+    fine_pos<R>(kx * g.tx_scale, N, ui, f);
+    const int k0 = (int)ceil(f - halfw);
+    for (int i = 0; i < g.W; ++i) {
+      const R phi = es_kernel((R)(k0 + i) * inv_halfw - f * inv_halfw, beta);
+      lds_add(&buf[(ui + k0 + i) & (N - 1)], phi * c);
+    }
+  }
+  __syncthreads();
+  if (stage == 0) {
+    for (int i = threadIdx.x; i < N; i += NT) out[(size_t)n * N + i] = buf[i];
+    return;
+  }
+  lds_fft<+1, N, NT>(buf, t.twx);
+  const int mx = g.mx;
+  for (int jx = threadIdx.x; jx < mx; jx += NT) {
+    const cplx<R> v = buf[(jx - mx / 2) & (N - 1)];
+    out[(size_t)n * mx + jx] = t.deapx[jx] * v;
+  }
+}
+
+// Azimuth stage: CB range columns per workgroup.  Spread every slice's range spectrum
+// value at the slice's azimuth position (taps precomputed per slice), inverse FFT along
+// azimuth, keep the centred my bins, divide by the kernel transform, write the image
+// columns (range-major, contiguous).
+template <typename R, int LOGN, int NT>
+__global__ __launch_bounds__(NT) void k_fwd_cols(Geo g, Tab<R> t, int cb, const cplx<R>* __restrict__ hx,
+                                                 cplx<R>* __restrict__ img) {
+  constexpr int N = 1 << LOGN;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem);
+  const int c0 = blockIdx.x * cb;
+  const int ncol = min(cb, g.mx - c0);
+  for (int i = threadIdx.x; i < cb * N; i += NT) buf[i] = {0, 0};
+  __syncthreads();
+  const int W = g.W;
+  const int total = g.n_pulses * ncol;
+  for (int idx = threadIdx.x; idx < total; idx += NT) {
+    const int n = idx / ncol, c = idx - n * ncol;
+    const cplx<R> v = hx[(size_t)n * g.mx + c0 + c];
+    const int ys = t.ystart[n];
+    const R* tap = t.ytap + (size_t)n * W;
+    cplx<R>* col = buf + c * N;
+    for (int i = 0; i < W; ++i) lds_add(&col[(ys + i) & (N - 1)], tap[i] * v);
+  }
+  __syncthreads();
+  for (int c = 0; c < ncol; ++c) lds_fft<+1, N, NT>(buf + c * N, t.twy);
+  const int my = g.my;
+  for (int c = 0; c < ncol; ++c) {
+    const cplx<R>* col = buf + c * N;
+    cplx<R>* o = img + (size_t)(c0 + c) * my;
+    for (int jy = threadIdx.x; jy < my; jy += NT) o[jy] = t.deapy[jy] * col[(jy - my / 2) & (N - 1)];
+  }
+}
+
+// ============================================================================ adjoint
+// Azimuth stage, type 2: per range column, divide by the kernel transform, zero-pad to
+// the fine grid, forward FFT (sign -), and interpolate at every slice's azimuth position.
+template <typename R, int LOGN, int NT>
+__global__ __launch_bounds__(NT) void k_adj_cols(Geo g, Tab<R> t, int cb, const cplx<R>* __restrict__ cot,
+                                                 cplx<R>* __restrict__ hx) {
+  constexpr int N = 1 << LOGN;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem);
+  const int c0 = blockIdx.x * cb;
+  const int ncol = min(cb, g.mx - c0);
+  const int my = g.my;
+  for (int c = 0; c < ncol; ++c) {
+    const cplx<R>* in = cot + (size_t)(c0 + c) * my;
+    for (int i = threadIdx.x; i < N; i += NT) {
+      const int jp = i < N / 2 ? i : i - N;  // signed bin
+      const int jy = jp + my / 2;
+      buf[c * N + i] = (jy >= 0 && jy < my) ? t.deapy[jy] * in[jy] : cplx<R>{0, 0};
+    }
+  }
+  __syncthreads();
+  for (int c = 0; c < ncol; ++c) lds_fft<-1, N, NT>(buf + c * N, t.twy);
+  const int W = g.W;
+  const int total = g.n_pulses * ncol;
+  for (int idx = threadIdx.x; idx < total; idx += NT) {
+    const int n = idx / ncol, c = idx - n * ncol;
+    const int ys = t.ystart[n];
+    const R* tap = t.ytap + (size_t)n * W;
+    const cplx<R>* col = buf + c * N;
+    cplx<R> acc = {0, 0};
+    for (int i = 0; i < W; ++i) acc = acc + tap[i] * col[(ys + i) & (N - 1)];
+    hx[(size_t)n * g.mx + c0 + c] = acc;
+  }
+}
+
+// Range stage, type 2: per slice, divide by the kernel transform, zero-pad, forward FFT
+// (sign -), interpolate at every sample, apply D^T and exp(-i psi), and reduce the
+// per-slice phase gradient sum_p Re(conj(g'_p) i s'_p) = sum_p (g_i s_r - g_r s_i).
+template <typename R, int LOGN, int NT>
+__global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, const cplx<R>* __restrict__ hx,
+                                                 const void* __restrict__ samples, const R* __restrict__ phase,
+                                                 const R* __restrict__ dalong, const R* __restrict__ w,
+                                                 cplx<R>* __restrict__ grad_s, R* __restrict__ grad_phase,
+                                                 R* __restrict__ grad_dalong) {
+  constexpr int N = 1 << LOGN;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem);
+  cplx<R>* gbuf = buf + N;  // FFR only: interpolated values of the slice
+  const int n = blockIdx.x;
+  const int mx = g.mx;
+  const cplx<R>* in = hx + (size_t)n * mx;
+  for (int i = threadIdx.x; i < N; i += NT) {
+    const int jp = i < N / 2 ? i : i - N;
+    const int jx = jp + mx / 2;
+    buf[i] = (jx >= 0 && jx < mx) ? t.deapx[jx] * in[jx] : cplx<R>{0, 0};
+  }
+  __syncthreads();
+  lds_fft<-1, N, NT>(buf, t.twx);
+  const cplx<R> rot = row_rotation(t, phase, dalong, n);
+  const double ku = t.ku[n];
+  const R halfw = (R)(0.5 * g.W), inv_halfw = (R)(2.0 / g.W), beta = (R)g.beta;
+  const size_t base = (size_t)n * g.n_freq;
+  const bool ffr = g.weighting == 2;
+  const bool want_phase = grad_phase || grad_dalong;
+  double acc_phase = 0.0;
+  for (int p = threadIdx.x; p < g.n_freq; p += NT) {
+    const double kx = stolt_kx(t.k[p], ku);
+    int ui;
+    R f;
+    fine_pos<R>(kx * g.tx_scale, N, ui, f);
+    const int k0 = (int)ceil(f - halfw);
+    cplx<R> a = {0, 0};
+    for (int i = 0; i < g.W; ++i) {
+      const R phi = es_kernel((R)(k0 + i) * inv_halfw - f * inv_halfw, beta);
+      a = a + phi * buf[(ui + k0 + i) & (N - 1)];
+    }
+    if (ffr) {
+      gbuf[p] = a;
+      continue;
+    }
+    const R wt = w ? w[base + p] : diag_weight<R>(g, t, ku, p, lattice_coord(kx, g.fov_x));
+    const cplx<R> gs = cmulc(wt * a, rot);  // exp(-i psi) D^T A^H
+    grad_s[base + p] = gs;
+    if (want_phase) {
+      const cplx<R> s = load_sample<R>(samples, stype, base + p);
+      acc_phase += (double)gs.y * (double)s.x - (double)gs.x * (double)s.y;
+    }
+  }
+  if (ffr) {
+    __syncthreads();
+    const int r = g.band_r;
+    for (int p = threadIdx.x; p < g.n_freq; p += NT) {
+      cplx<R> a = {0, 0};
+      for (int o = -r; o <= r; ++o) {  // (D^T x)_p = sum_o D_{p+o, p} x_{p+o}
+        const int pp = p + o;
+        if (pp >= 0 && pp < g.n_freq) a = a + w[(base + pp) * (2 * r + 1) + (r - o)] * gbuf[pp];
+      }
+      const cplx<R> gs = cmulc(a, rot);
+      grad_s[base + p] = gs;
+      if (want_phase) {
+        const cplx<R> s = load_sample<R>(samples, stype, base + p);
+        acc_phase += (double)gs.y * (double)s.x - (double)gs.x * (double)s.y;
+      }
+    }
+  }
+  if (want_phase) {
+    const double tot = block_sum<NT>(acc_phase);
+    if (threadIdx.x == 0) {
+      if (grad_phase) grad_phase[n] = (R)tot;
+      if (grad_dalong) grad_dalong[n] = (R)((double)t.ky[n] * tot);
+    }
+  }
+}
+
+// ============================================================================ weights
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void k_weights(Geo g, Tab<R> t, R* __restrict__ w,
+                                                unsigned long long* __restrict__ kept_partial) {
+  const size_t total = (size_t)g.n_pulses * g.n_freq;
+  unsigned long long kept = 0;
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < total; i += (size_t)gridDim.x * NT) {
+    const int n = (int)(i / g.n_freq), p = (int)(i - (size_t)n * g.n_freq);
+    const double ku = t.ku[n];
+    const double lam = lattice_coord(stolt_kx(t.k[p], ku), g.fov_x);
+    const R v = diag_weight<R>(g, t, ku, p, lam);
+    if (w) w[i] = v;
+    kept += (v != (R)0) ? 1ull : 0ull;
+  }
+  const double tot = block_sum<NT>((double)kept);
+  if (threadIdx.x == 0 && kept_partial) kept_partial[blockIdx.x] = (unsigned long long)tot;
+}
+
+__global__ void k_sum_u64(const unsigned long long* __restrict__ parts, int n, long long* out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    unsigned long long s = 0;
+    for (int i = 0; i < n; ++i) s += parts[i];
+    *out = (long long)s;
+  }
+}
+
+// ============================================================================ plain FFR
+// Band of the truncated frame product of every slice, row p, columns p-b..p+b:
+// G~_{p,p'} = sum over integers m with |m - lam_p| < q and |m - lam_p'| < q of
+// R_Psi(m - lam_p) R_W(m - lam_p').
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void k_ffr_build(Geo g, Tab<R> t, double* __restrict__ gband) {
+  const int b = g.band_b, wdt = 2 * b + 1;
+  const size_t total = (size_t)g.n_pulses * g.n_freq;
+  const int K = (int)ceil(g.q) + 1;
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < total; i += (size_t)gridDim.x * NT) {
+    const int n = (int)(i / g.n_freq), p = (int)(i - (size_t)n * g.n_freq);
+    const double ku = t.ku[n];
+    const double lp = lattice_coord(stolt_kx(t.k[p], ku), g.fov_x);
+    const double fl = floor(lp);
+    for (int o = -b; o <= b; ++o) {
+      const int pp = p + o;
+      double acc = 0.0;
+      if (pp >= 0 && pp < g.n_freq) {
+        const double lq = lattice_coord(stolt_kx(t.k[pp], ku), g.fov_x);
+        for (int k = -K; k <= K; ++k) {
+          const double m = fl + (double)k;
+          const double d1 = m - lp, d2 = m - lq;
+          if (fabs(d1) < g.q && fabs(d2) < g.q) acc += r_psi(d1, g) * r_w(d2, g);
+        }
+      }
+      gband[i * wdt + (b + o)] = acc;
+    }
+  }
+}
+
+// One thread per slice: LU without pivoting of the banded frame product (half
+// bandwidth b), selected inversion of the band of its inverse (Takahashi recurrences
+// UZ = L^-1 and ZL = U^-1, which close within the band), and the band B_r of the
+// inverse (= pinv for a full-rank product).  status[0] is set to 1 on a vanishing pivot.
+template <typename R>
+__global__ void k_ffr_solve(Geo g, double* __restrict__ gband, double* __restrict__ zband,
+                            R* __restrict__ dband, int* __restrict__ status) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.n_pulses) return;
+  const int P = g.n_freq, b = g.band_b, wdt = 2 * b + 1, r = g.band_r;
+  double* A = gband + (size_t)n * P * wdt;
+  double* Z = zband + (size_t)n * P * wdt;
+#define BA(i, j) A[(size_t)(i) * wdt + (b + (j) - (i))]
+#define BZ(i, j) Z[(size_t)(i) * wdt + (b + (j) - (i))]
+  double scale = 0.0;
+  for (int i = 0; i < P; ++i) scale = fmax(scale, fabs(BA(i, i)));
+  bool bad = false;
+  for (int k = 0; k < P; ++k) {
+    const double piv = BA(k, k);
+    if (!(fabs(piv) > 1e-12 * scale)) {
+      bad = true;
+      break;
+    }
+    const int hi = min(k + b, P - 1);
+    for (int i = k + 1; i <= hi; ++i) {
+      const double l = BA(i, k) / piv;
+      BA(i, k) = l;
+      for (int j = k + 1; j <= hi; ++j) BA(i, j) -= l * BA(k, j);
+    }
+  }
+  if (bad) {
+    atomicExch(status, 1);
+    for (int p = 0; p < P; ++p)
+      for (int o = 0; o < 2 * r + 1; ++o) dband[((size_t)n * P + p) * (2 * r + 1) + o] = (R)0;
+    return;
+  }
+  for (int i = P - 1; i >= 0; --i) {
+    const int hi = min(i + b, P - 1);
+    for (int j = hi; j >= i; --j) {
+      double s = (i == j) ? 1.0 : 0.0;
+      for (int k = i + 1; k <= hi; ++k) s -= BA(i, k) * BZ(k, j);
+      BZ(i, j) = s / BA(i, i);
+    }
+    const int lo = max(i - b, 0);
+    for (int j = i - 1; j >= lo; --j) {
+      double s = 0.0;
+      const int khi = min(j + b, P - 1);
+      for (int k = j + 1; k <= khi; ++k) s -= BZ(i, k) * BA(k, j);
+      BZ(i, j) = s;
+    }
+  }
+  for (int p = 0; p < P; ++p)
+    for (int o = -r; o <= r; ++o) {
+      const int pp = p + o;
+      dband[((size_t)n * P + p) * (2 * r + 1) + (r + o)] = (pp >= 0 && pp < P) ? (R)BZ(p, pp) : (R)0;
+    }
+#undef BA
+#undef BZ
+}
+
+// ============================================================================ entropy
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void k_entropy_partial(const cplx<R>* __restrict__ img, size_t count,
+                                                        double* __restrict__ partials) {
+  double s = 0.0, tl = 0.0;
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < count; i += (size_t)gridDim.x * NT) {
+    const cplx<R> v = img[i];
+    const R a = v.x * v.x + v.y * v.y;
+    s += (double)a;
+    if (a > (R)0) tl += (double)(a * log(a));
+  }
+  s = block_sum<NT>(s);
+  tl = block_sum<NT>(tl);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = s;
+    partials[2 * blockIdx.x + 1] = tl;
+  }
+}
+
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void k_entropy_finish(const cplx<R>* __restrict__ img, size_t count,
+                                                       const double* __restrict__ partials, int nparts,
+                                                       double* __restrict__ loss, cplx<R>* __restrict__ grad) {
+  double s = 0.0, tl = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += NT) {
+    s += partials[2 * i];
+    tl += partials[2 * i + 1];
+  }
+  s = block_sum<NT>(s);
+  tl = block_sum<NT>(tl);
+  const double E = (s > 0.0) ? log(s) - tl / s : 0.0;  // E = ln S - (1/S) sum a ln a
+  if (blockIdx.x == 0 && threadIdx.x == 0) *loss = E;
+  if (!grad) return;
+  const R logS = (R)log(s), Er = (R)E, sc = (R)(-2.0 / s);
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < count; i += (size_t)gridDim.x * NT) {
+    const cplx<R> v = img[i];
+    const R a = v.x * v.x + v.y * v.y;
+    grad[i] = a > (R)0 ? (sc * (log(a) - logS + Er)) * v : cplx<R>{0, 0};
+  }
+}
+
+// ============================================================================ debug FFT
+template <typename R, int SIGN, int LOGN, int NT>
+__global__ __launch_bounds__(NT) void k_fft(const cplx<R>* __restrict__ in, cplx<R>* out, const cplx<R>* __restrict__ tw) {
+  constexpr int N = 1 << LOGN;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem);
+  const size_t off = (size_t)blockIdx.x * N;
+  for (int i = threadIdx.x; i < N; i += NT) buf[i] = in[off + i];
+  __syncthreads();
+  lds_fft<SIGN, N, NT>(buf, tw);
+  for (int i = threadIdx.x; i < N; i += NT) out[off + i] = buf[i];
+}
+
+// ============================================================================ launchers
+template <int LOGN>
+constexpr int nt_for() {
+  return LOGN <= 8 ? 64 : (LOGN <= 11 ? 256 : (LOGN == 12 ? 256 : (LOGN == 13 ? 512 : 1024)));
+}
+
+static hipError_t allow_lds(const void* fn, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+size_t max_dynamic_lds() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) == hipSuccess && v > 0)
+    return (size_t)v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+    return (size_t)v;
+  return 65536;
+}
+
+#define TFFR_LOGN_CASE(v, ...) \
+  case v: {                     \
+    constexpr int L = v;        \
+    __VA_ARGS__                 \
+  }
+#define TFFR_LOGN_DISPATCH(logn, ...)     \
+  switch (logn) {                         \
+    TFFR_LOGN_CASE(6, __VA_ARGS__)        \
+    TFFR_LOGN_CASE(7, __VA_ARGS__)        \
+    TFFR_LOGN_CASE(8, __VA_ARGS__)        \
+    TFFR_LOGN_CASE(9, __VA_ARGS__)        \
+    TFFR_LOGN_CASE(10, __VA_ARGS__)       \
+    TFFR_LOGN_CASE(11, __VA_ARGS__)       \
+    TFFR_LOGN_CASE(12, __VA_ARGS__)       \
+    TFFR_LOGN_CASE(13, __VA_ARGS__)       \
+    TFFR_LOGN_CASE(14, __VA_ARGS__)       \
+    default:                              \
+      return hipErrorInvalidValue;        \
+  }
+
+template <typename R>
+hipError_t launch_fwd_rows(const Geo& g, const Tab<R>& t, int stype, const void* samples, const R* phase,
+                           const R* dalong, const R* w, cplx<R>* out, int stage, hipStream_t st) {
+  const size_t lds = sizeof(cplx<R>) << g.lognfx;
+  TFFR_LOGN_DISPATCH(g.lognfx, {
+    constexpr int NT = nt_for<L>();
+    auto fn = k_fwd_rows<R, L, NT>;
+    hipError_t e = allow_lds((const void*)fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3(g.n_pulses), dim3(NT), lds, st, g, t, stype, samples, phase, dalong, w, out, stage);
+    return hipGetLastError();
+  })
+}
+
+template <typename R>
+hipError_t launch_fwd_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>* hx, cplx<R>* img, hipStream_t st) {
+  const size_t lds = (sizeof(cplx<R>) << g.lognfy) * cb;
+  const int grid = (g.mx + cb - 1) / cb;
+  TFFR_LOGN_DISPATCH(g.lognfy, {
+    constexpr int NT = nt_for<L>();
+    auto fn = k_fwd_cols<R, L, NT>;
+    hipError_t e = allow_lds((const void*)fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), lds, st, g, t, cb, hx, img);
+    return hipGetLastError();
+  })
+}
+
+template <typename R>
+hipError_t launch_adj_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>* cot, cplx<R>* hx, hipStream_t st) {
+  const size_t lds = (sizeof(cplx<R>) << g.lognfy) * cb;
+  const int grid = (g.mx + cb - 1) / cb;
+  TFFR_LOGN_DISPATCH(g.lognfy, {
+    constexpr int NT = nt_for<L>();
+    auto fn = k_adj_cols<R, L, NT>;
+    hipError_t e = allow_lds((const void*)fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), lds, st, g, t, cb, cot, hx);
+    return hipGetLastError();
+  })
+}
+
+template <typename R>
+hipError_t launch_adj_rows(const Geo& g, const Tab<R>& t, int stype, const cplx<R>* hx, const void* samples,
+                           const R* phase, const R* dalong, const R* w, cplx<R>* grad_s, R* grad_phase,
+                           R* grad_dalong, hipStream_t st) {
+  size_t lds = sizeof(cplx<R>) << g.lognfx;
+  if (g.weighting == 2) lds += sizeof(cplx<R>) * (size_t)g.n_freq;
+  TFFR_LOGN_DISPATCH(g.lognfx, {
+    constexpr int NT = nt_for<L>();
+    auto fn = k_adj_rows<R, L, NT>;
+    hipError_t e = allow_lds((const void*)fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3(g.n_pulses), dim3(NT), lds, st, g, t, stype, hx, samples, phase, dalong, w,
+                       grad_s, grad_phase, grad_dalong);
+    return hipGetLastError();
+  })
+}
+
+template <typename R>
+hipError_t launch_weights(const Geo& g, const Tab<R>& t, R* w, unsigned long long* kept_partial, int nblocks,
+                          hipStream_t st) {
+  hipLaunchKernelGGL((k_weights<R, 256>), dim3(nblocks), dim3(256), 0, st, g, t, w, kept_partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_u64(const unsigned long long* parts, int n, long long* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_u64, dim3(1), dim3(64), 0, st, parts, n, out);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_ffr(const Geo& g, const Tab<R>& t, double* gband, double* zband, R* dband, int* status,
+                      hipStream_t st) {
+  const size_t total = (size_t)g.n_pulses * g.n_freq;
+  const int blocks = (int)std::min<size_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL((k_ffr_build<R, 256>), dim3(blocks), dim3(256), 0, st, g, t, gband);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_ffr_solve<R>), dim3((g.n_pulses + 63) / 64), dim3(64), 0, st, g, gband, zband, dband,
+                     status);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_entropy(const Geo& g, const cplx<R>* img, double* partials, int nparts, double* loss,
+                          cplx<R>* grad, hipStream_t st) {
+  const size_t count = (size_t)g.mx * g.my;
+  hipLaunchKernelGGL((k_entropy_partial<R, 256>), dim3(nparts), dim3(256), 0, st, img, count, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int gblocks = grad ? nparts : 1;
+  hipLaunchKernelGGL((k_entropy_finish<R, 256>), dim3(gblocks), dim3(256), 0, st, img, count, partials, nparts,
+                     loss, grad);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_fft(int log2n, int batch, int sign, const cplx<R>* in, cplx<R>* out, const cplx<R>* tw,
+                      hipStream_t st) {
+  const size_t lds = sizeof(cplx<R>) << log2n;
+  TFFR_LOGN_DISPATCH(log2n, {
+    constexpr int NT = nt_for<L>();
+    if (sign > 0) {
+      auto fn = k_fft<R, +1, L, NT>;
+      hipError_t e = allow_lds((const void*)fn, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(fn, dim3(batch), dim3(NT), lds, st, in, out, tw);
+    } else {
+      auto fn = k_fft<R, -1, L, NT>;
+      hipError_t e = allow_lds((const void*)fn, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(fn, dim3(batch), dim3(NT), lds, st, in, out, tw);
+    }
+    return hipGetLastError();
+  })
+}
+
+#define TFFR_INSTANTIATE(R)                                                                                     \
+  template hipError_t launch_fwd_rows<R>(const Geo&, const Tab<R>&, int, const void*, const R*, const R*,     \
+                                         const R*, cplx<R>*, int, hipStream_t);                                \
+  template hipError_t launch_fwd_cols<R>(const Geo&, const Tab<R>&, int, const cplx<R>*, cplx<R>*, hipStream_t); \
+  template hipError_t launch_adj_cols<R>(const Geo&, const Tab<R>&, int, const cplx<R>*, cplx<R>*, hipStream_t); \
+  template hipError_t launch_adj_rows<R>(const Geo&, const Tab<R>&, int, const cplx<R>*, const void*, const R*, \
+                                         const R*, const R*, cplx<R>*, R*, R*, hipStream_t);                   \
+  template hipError_t launch_weights<R>(const Geo&, const Tab<R>&, R*, unsigned long long*, int, hipStream_t);  \
+  template hipError_t launch_ffr<R>(const Geo&, const Tab<R>&, double*, double*, R*, int*, hipStream_t);       \
+  template hipError_t launch_entropy<R>(const Geo&, const cplx<R>*, double*, int, double*, cplx<R>*,          \
+                                        hipStream_t);                                                          \
+  template hipError_t launch_fft<R>(int, int, int, const cplx<R>*, cplx<R>*, const cplx<R>*, hipStream_t);
+
+TFFR_INSTANTIATE(float)
+TFFR_INSTANTIATE(double)
+
+}  // namespace tffr

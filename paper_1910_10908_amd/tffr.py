@@ -1,0 +1,244 @@
+"""Python binding of libtffr with the same names as the C ABI, plus torch.autograd wrappers.
+
+PyTorch only supplies device memory and the current stream; every step of the path
+runs in libtffr's HIP kernels.  Tensors must be contiguous and on the plan's device.
+"""
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (C64, C64_FP16IN, C128, THRESH_CORRELATION, THRESH_LITERAL, W_FFR, W_NONE, W_QUAD,  # noqa: F401
+                   W_TFFR, W_USER, Params)
+
+_DT = {C64: (torch.complex64, torch.float32), C128: (torch.complex128, torch.float64),
+       C64_FP16IN: (torch.complex64, torch.float32)}
+
+
+def default_params(**kw):
+    p = Params()
+    _lib.load().tffr_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def tffr_validate(params, k, ku):
+    k = np.ascontiguousarray(k, dtype=np.float64)
+    ku = np.ascontiguousarray(ku, dtype=np.float64)
+    return _lib.load().tffr_validate(ctypes.byref(params), _dptr(k), _dptr(ku))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """tffr_plan_create / tffr_plan_destroy, and the calls that take a plan."""
+
+    def __init__(self, params, k, ku, device="cuda:0"):
+        self.lib = _lib.load()
+        self.params = params
+        self.device = torch.device(device)
+        self.k = np.ascontiguousarray(k, dtype=np.float64)
+        self.ku = np.ascontiguousarray(ku, dtype=np.float64)
+        if self.k.size != params.n_freq or self.ku.size != params.n_pulses:
+            raise ValueError("k / ku sizes do not match params")
+        self.ctype, self.rtype = _DT[params.dtype]
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(self.lib.tffr_plan_create(ctypes.byref(params), _dptr(self.k), _dptr(self.ku),
+                                                 ctypes.byref(h)), "tffr_plan_create")
+        self.handle = h
+        nfx, nfy, hb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        beta = ctypes.c_double()
+        _lib.check(self.lib.tffr_plan_info(h, ctypes.byref(nfx), ctypes.byref(nfy), ctypes.byref(beta),
+                                           ctypes.byref(hb)))
+        self.nfine = (nfx.value, nfy.value)
+        self.beta = beta.value
+        self.ffr_halfband = hb.value
+        self.work = torch.empty(int(self.lib.tffr_workspace_bytes(h)), dtype=torch.uint8, device=self.device)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.tffr_plan_destroy(h)
+            self.handle = None
+
+    # ---------------------------------------------------------------- checks
+    @property
+    def shape_samples(self):
+        return (self.params.n_pulses, self.params.n_freq)
+
+    @property
+    def shape_image(self):
+        return (self.params.mx, self.params.my)
+
+    def _chk(self, t, shape, dtype, name):
+        if t is None:
+            return None
+        if tuple(t.shape) != tuple(shape) or t.dtype != dtype or not t.is_contiguous() or t.device != self.device:
+            raise ValueError(f"{name}: expected contiguous {dtype} {tuple(shape)} on {self.device}, got "
+                             f"{t.dtype} {tuple(t.shape)} on {t.device}")
+        return t
+
+    def _chk_samples(self, s):
+        if self.params.dtype == C64_FP16IN:
+            return self._chk(s, self.shape_samples + (2,), torch.float16, "samples")
+        return self._chk(s, self.shape_samples, self.ctype, "samples")
+
+    def _chk_weights(self, w):
+        if w is None:
+            return None
+        shape = self.shape_samples
+        if self.params.weighting == W_FFR:
+            shape = shape + (2 * self.params.band_r + 1,)
+        return self._chk(w, shape, self.rtype, "weights")
+
+    # ---------------------------------------------------------------- calls
+    def tffr_forward(self, samples, phase=None, dalong=None, user_w=None, out=None):
+        self._chk_samples(samples)
+        self._chk(phase, (self.params.n_pulses,), self.rtype, "phase")
+        self._chk(dalong, (self.params.n_pulses,), self.rtype, "dalong")
+        self._chk_weights(user_w)
+        if out is None:
+            out = torch.empty(self.shape_image, dtype=self.ctype, device=self.device)
+        self._chk(out, self.shape_image, self.ctype, "image")
+        _lib.check(self.lib.tffr_forward(self.handle, _ptr(samples), _ptr(phase), _ptr(dalong), _ptr(user_w),
+                                         _ptr(out), _ptr(self.work), _stream()), "tffr_forward")
+        return out
+
+    def tffr_adjoint(self, grad_image, samples=None, phase=None, dalong=None, user_w=None,
+                     want_phase=False, want_dalong=False, out=None):
+        self._chk(grad_image, self.shape_image, self.ctype, "grad_image")
+        self._chk_samples(samples)
+        self._chk(phase, (self.params.n_pulses,), self.rtype, "phase")
+        self._chk(dalong, (self.params.n_pulses,), self.rtype, "dalong")
+        self._chk_weights(user_w)
+        if out is None:
+            out = torch.empty(self.shape_samples, dtype=self.ctype, device=self.device)
+        self._chk(out, self.shape_samples, self.ctype, "grad_samples")
+        gph = torch.empty(self.params.n_pulses, dtype=self.rtype, device=self.device) if want_phase else None
+        gda = torch.empty(self.params.n_pulses, dtype=self.rtype, device=self.device) if want_dalong else None
+        _lib.check(self.lib.tffr_adjoint(self.handle, _ptr(grad_image), _ptr(samples), _ptr(phase), _ptr(dalong),
+                                         _ptr(user_w), _ptr(out), _ptr(gph), _ptr(gda), _ptr(self.work),
+                                         _stream()), "tffr_adjoint")
+        return out, gph, gda
+
+    def tffr_entropy(self, image, want_grad=True):
+        self._chk(image, self.shape_image, self.ctype, "image")
+        loss = torch.empty((), dtype=torch.float64, device=self.device)
+        grad = torch.empty_like(image) if want_grad else None
+        _lib.check(self.lib.tffr_entropy(self.handle, _ptr(image), _ptr(loss), _ptr(grad), _ptr(self.work),
+                                         _stream()), "tffr_entropy")
+        return loss, grad
+
+    def tffr_weights(self, out=None):
+        shape = self.shape_samples
+        if self.params.weighting == W_FFR:
+            shape = shape + (2 * self.params.band_r + 1,)
+        if out is None:
+            out = torch.empty(shape, dtype=self.rtype, device=self.device)
+        self._chk(out, shape, self.rtype, "weights")
+        _lib.check(self.lib.tffr_weights(self.handle, _ptr(out), _ptr(self.work), _stream()), "tffr_weights")
+        return out
+
+    def tffr_kept_count(self):
+        c = ctypes.c_int64()
+        _lib.check(self.lib.tffr_kept_count(self.handle, _ptr(self.work), ctypes.byref(c), _stream()),
+                   "tffr_kept_count")
+        return c.value
+
+    def tffr_debug_rows(self, samples, stage=1, phase=None, dalong=None, user_w=None):
+        self._chk_samples(samples)
+        n = self.nfine[0] if stage == 0 else self.params.mx
+        out = torch.empty((self.params.n_pulses, n), dtype=self.ctype, device=self.device)
+        _lib.check(self.lib.tffr_debug_rows(self.handle, stage, _ptr(samples), _ptr(phase), _ptr(dalong),
+                                            _ptr(user_w), _ptr(out), _stream()), "tffr_debug_rows")
+        return out
+
+
+def tffr_debug_fft(x, sign):
+    """Batched LDS FFT of the rows of x (complex64/complex128, power-of-two length)."""
+    lib = _lib.load()
+    x = x.contiguous()
+    n = x.shape[-1]
+    log2n = int(round(np.log2(n)))
+    dtype = C128 if x.dtype == torch.complex128 else C64
+    out = torch.empty_like(x)
+    _lib.check(lib.tffr_debug_fft(log2n, x.numel() // n, sign, dtype, _ptr(x), _ptr(out), _stream()),
+               "tffr_debug_fft")
+    return out
+
+
+# -------------------------------------------------------------------- autograd
+class _Forward(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, plan, samples, phase, dalong, user_w):
+        ctx.plan = plan
+        ctx.save_for_backward(samples, phase, dalong, user_w)
+        return plan.tffr_forward(samples, phase, dalong, user_w)
+
+    @staticmethod
+    def backward(ctx, grad_image):
+        plan = ctx.plan
+        samples, phase, dalong, user_w = ctx.saved_tensors
+        want_ph = phase is not None and ctx.needs_input_grad[2]
+        want_da = dalong is not None and ctx.needs_input_grad[3]
+        gs, gph, gda = plan.tffr_adjoint(grad_image.contiguous(), samples if (want_ph or want_da) else None,
+                                         phase, dalong, user_w, want_phase=want_ph, want_dalong=want_da)
+        return None, (gs if ctx.needs_input_grad[1] else None), gph, gda, None
+
+
+class _Adjoint(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, plan, image, user_w):
+        ctx.plan = plan
+        ctx.save_for_backward(user_w)
+        gs, _, _ = plan.tffr_adjoint(image, None, None, None, user_w)
+        return gs
+
+    @staticmethod
+    def backward(ctx, grad_samples):
+        (user_w,) = ctx.saved_tensors
+        return None, ctx.plan.tffr_forward(grad_samples.contiguous(), None, None, user_w), None
+
+
+class _Entropy(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, plan, image):
+        loss, grad = plan.tffr_entropy(image, want_grad=True)
+        ctx.save_for_backward(grad)
+        return loss
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return None, grad * g.to(grad.real.dtype)
+
+
+def tffr_image(plan, samples, phase=None, dalong=None, user_w=None):
+    """Differentiable image formation: samples, phase, dalong -> image (range-major)."""
+    return _Forward.apply(plan, samples, phase, dalong, user_w)
+
+
+def tffr_adjoint_op(plan, image, user_w=None):
+    """Differentiable adjoint operator A^H (its backward is the forward operator)."""
+    return _Adjoint.apply(plan, image, user_w)
+
+
+def image_entropy(plan, image):
+    """Differentiable image entropy (FP64 scalar)."""
+    return _Entropy.apply(plan, image)

@@ -1,0 +1,251 @@
+"""GPU parity of the HIP path against the FP64 oracle (and of single stages against
+independent CPU references of that stage).  Every call goes through the C ABI."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import entropy as OE
+from oracle import pipeline as OP
+from oracle import weights as OW
+from paper_1910_10908_amd import tffr as T
+from tests.gpu_helpers import DEV, Case, peak_db, rel_l2, tol_for
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu(gpu):
+    print(flush=True)
+    yield
+
+
+# ---------------------------------------------------------------- single stages
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+@pytest.mark.parametrize("log2n", [6, 7, 8, 9, 10, 11, 12, 13])
+@pytest.mark.parametrize("sign", [1, -1])
+def test_lds_fft_vs_numpy(log2n, sign, dtype):
+    print(f"fft log2n={log2n} sign={sign} {dtype}", flush=True)
+    rng = np.random.default_rng(log2n)
+    n = 1 << log2n
+    x = rng.standard_normal((3, n)) + 1j * rng.standard_normal((3, n))
+    xt = torch.as_tensor(x, dtype=dtype, device=DEV)
+    got = T.tffr_debug_fft(xt, sign).cpu().numpy()
+    xr = xt.cpu().numpy().astype(np.complex128)
+    ref = np.fft.ifft(xr, axis=-1) * n if sign > 0 else np.fft.fft(xr, axis=-1)
+    tol = 1e-6 if dtype == torch.complex64 else 1e-13
+    assert rel_l2(got, ref) < tol
+
+
+def es_spread_rows_cpu(case, c):
+    """Independent FP64 reference of the range gridding: c[n,p] spread with the plan's
+    ES kernel (beta, width from the plan) onto the periodic fine row."""
+    kx, ky, lam, X, Y = case.prob.geometry()
+    nf = case.plan.nfine[0]
+    W, beta = case.prm.kernel_width, case.plan.beta
+    t = kx * case.prm.fov_x / (2 * np.pi * case.prm.mx)
+    u = (t - np.floor(t)) * nf
+    out = np.zeros((kx.shape[0], nf), complex)
+    for n in range(kx.shape[0]):
+        for p in range(kx.shape[1]):
+            for g in range(int(np.floor(u[n, p] - W / 2)) - 1, int(np.ceil(u[n, p] + W / 2)) + 2):
+                z = (g - u[n, p]) / (W / 2)
+                if abs(z) < 1:
+                    out[n, g % nf] += c[n, p] * np.exp(beta * (np.sqrt(1 - z * z) - 1))
+    return out
+
+
+@pytest.mark.parametrize("weighting", [T.W_NONE, T.W_TFFR, T.W_QUAD])
+def test_range_gridding_stage(weighting):
+    print(f"gridding stage weighting={weighting}", flush=True)
+    case = Case(6, 40, 32, weighting=weighting, seed=3)
+    s, st = case.samples()
+    phase = case.rng.normal(0, 0.5, 6)
+    got = case.plan.tffr_debug_rows(st, stage=0, phase=case.real(phase)).cpu().numpy()
+    c = OP.weighted_samples(case.prob, s, case.rounded(phase))
+    ref = es_spread_rows_cpu(case, c)
+    assert rel_l2(got, ref) < 2e-6
+
+
+# ---------------------------------------------------------------- weights
+@pytest.mark.parametrize("tau,mode", [(0.97, OW.THRESH_LITERAL), (1.03, OW.THRESH_LITERAL),
+                                      (0.97, OW.THRESH_CORRELATION), (0.9, OW.THRESH_CORRELATION)])
+@pytest.mark.parametrize("dtype", [T.C64, T.C128])
+def test_tffr_weights_and_kept_count(tau, mode, dtype):
+    print(f"tffr weights tau={tau} mode={mode} dtype={dtype}", flush=True)
+    case = Case(64, 512, 128, fov=400.0, weighting=T.W_TFFR, tau=tau, thresh_mode=mode, dtype=dtype)
+    got = case.plan.tffr_weights().cpu().numpy()
+    kx, ky, lam, X, Y = case.prob.geometry()
+    ref, kept = OW.tffr_weights(lam, 0.01, 3.0, tau, mode)
+    # decisions are taken in FP64 near the threshold: identical kept sets
+    assert np.array_equal(got != 0, kept)
+    assert case.plan.tffr_kept_count() == int(kept.sum())
+    # FP64: the closed forms cancel a(1 - e^{-a/2}) ~ a^2/2 out of terms of size a near
+    # d = 0, a condition number ~ 2/a = 200, so two correct FP64 evaluations that round
+    # sin/cos differently agree to ~ 200 * 16 eps ~ 1e-12.  FP32: polynomial + rounding.
+    tol = 1e-12 if dtype == T.C128 else 3e-7
+    assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref)) + 1e-300
+
+
+def test_quad_weights():
+    case = Case(16, 300, 64, fov=400.0, weighting=T.W_QUAD)
+    got = case.plan.tffr_weights().cpu().numpy()
+    kx, ky, lam, X, Y = case.prob.geometry()
+    ref = OW.quad_weights(lam)
+    assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-6
+    assert case.plan.tffr_kept_count() == 16 * 300
+
+
+@pytest.mark.parametrize("dtype", [T.C64, T.C128])
+def test_ffr_weights(dtype):
+    print(f"ffr weights dtype={dtype}", flush=True)
+    case = Case(8, 128, 128, fov=40.0, weighting=T.W_FFR, dtype=dtype)
+    got = case.plan.tffr_weights().cpu().numpy()
+    kx, ky, lam, X, Y = case.prob.geometry()
+    ref = OW.ffr_weights(lam, 0.01, 3.0, 2)
+    tol = 1e-12 if dtype == T.C128 else 1e-6
+    assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------- forward / adjoint
+SIZES = [(8, 16, 16), (64, 128, 128), (33, 100, 50), (5, 257, 34)]
+
+
+@pytest.mark.parametrize("size", SIZES)
+@pytest.mark.parametrize("dtype,width", [(T.C64, 7), (T.C128, 14)])
+@pytest.mark.parametrize("weighting", [T.W_TFFR, T.W_QUAD, T.W_NONE])
+def test_forward_parity(size, dtype, width, weighting):
+    print(f"forward size={size} dtype={dtype} w={width} weighting={weighting}", flush=True)
+    case = Case(*size, weighting=weighting, dtype=dtype, width=width, seed=11)
+    s, st = case.samples()
+    phase = case.rng.normal(0, 0.5, size[0])
+    dal = case.rng.normal(0, 0.004, size[0])
+    got = case.plan.tffr_forward(st, case.real(phase), case.real(dal)).cpu().numpy()
+    ref = OP.image(case.prob, s, case.rounded(phase), case.rounded(dal))
+    err = rel_l2(got, ref)
+    print(f"  rel-L2 {err:.3e} peak {peak_db(got, ref):.1f} dB", flush=True)
+    assert err < tol_for(case)
+
+
+@pytest.mark.parametrize("size", SIZES)
+@pytest.mark.parametrize("dtype,width", [(T.C64, 7), (T.C128, 14)])
+@pytest.mark.parametrize("weighting", [T.W_TFFR, T.W_QUAD])
+def test_adjoint_parity(size, dtype, width, weighting):
+    print(f"adjoint size={size} dtype={dtype} w={width} weighting={weighting}", flush=True)
+    case = Case(*size, weighting=weighting, dtype=dtype, width=width, seed=12)
+    s, st = case.samples()
+    phase = case.rng.normal(0, 0.5, size[0])
+    dal = case.rng.normal(0, 0.004, size[0])
+    y = case.image_np()
+    yt = torch.as_tensor(y, dtype=case.ctype, device=DEV)
+    gs, gph, gda = case.plan.tffr_adjoint(yt, st, case.real(phase), case.real(dal), want_phase=True,
+                                          want_dalong=True)
+    yr = yt.cpu().numpy().astype(np.complex128)
+    rgs, rgph, rgda = OP.backward(case.prob, yr, s, case.rounded(phase), case.rounded(dal))
+    e1 = rel_l2(gs.cpu().numpy(), rgs)
+    e2 = np.max(np.abs(gph.cpu().numpy() - rgph)) / np.max(np.abs(rgph))
+    e3 = np.max(np.abs(gda.cpu().numpy() - rgda)) / np.max(np.abs(rgda))
+    print(f"  grad_s rel-L2 {e1:.3e}  dphi {e2:.3e}  ddu {e3:.3e}", flush=True)
+    tol = tol_for(case)
+    assert e1 < tol and e2 < 20 * tol and e3 < 20 * tol
+
+
+@pytest.mark.parametrize("dtype,width", [(T.C64, 7), (T.C128, 14)])
+def test_ffr_forward_adjoint(dtype, width):
+    print(f"ffr fwd/adj dtype={dtype}", flush=True)
+    case = Case(64, 128, 128, weighting=T.W_FFR, dtype=dtype, width=width, seed=13)
+    s, st = case.samples()
+    phase = case.rng.normal(0, 0.5, 64)
+    got = case.plan.tffr_forward(st, case.real(phase)).cpu().numpy()
+    ref = OP.image(case.prob, s, case.rounded(phase))
+    assert rel_l2(got, ref) < tol_for(case)
+    y = case.image_np()
+    yt = torch.as_tensor(y, dtype=case.ctype, device=DEV)
+    gs, gph, _ = case.plan.tffr_adjoint(yt, st, case.real(phase), want_phase=True)
+    rgs, rgph, _ = OP.backward(case.prob, yt.cpu().numpy().astype(np.complex128), s, case.rounded(phase))
+    assert rel_l2(gs.cpu().numpy(), rgs) < tol_for(case)
+    assert np.max(np.abs(gph.cpu().numpy() - rgph)) < 20 * tol_for(case) * np.max(np.abs(rgph))
+    # the explicit weights of tffr_weights give the same image as the plan's cached D
+    D = case.plan.tffr_weights()
+    got2 = case.plan.tffr_forward(st, case.real(phase), user_w=D).cpu().numpy()
+    assert rel_l2(got2, got) < 1e-6
+
+
+def test_adjoint_identity_gpu():
+    case = Case(48, 200, 96, fov=100.0, seed=14)
+    s, st = case.samples()
+    y = torch.as_tensor(case.image_np(), dtype=case.ctype, device=DEV)
+    Ax = case.plan.tffr_forward(st)
+    Ahy, _, _ = case.plan.tffr_adjoint(y)
+    lhs = torch.vdot(y.flatten().to(torch.complex128), Ax.flatten().to(torch.complex128))
+    rhs = torch.vdot(Ahy.flatten().to(torch.complex128), st.flatten().to(torch.complex128))
+    rel = float(abs(lhs - rhs) / (torch.linalg.norm(Ax.double()) * torch.linalg.norm(y.double())))
+    assert rel < 1e-6
+
+
+def test_entropy_and_gradients():
+    print("entropy + autograd", flush=True)
+    case = Case(64, 128, 128, seed=15)
+    s, st = case.samples()
+    phase = case.rng.normal(0, 0.5, 64)
+    dal = case.rng.normal(0, 0.004, 64)
+    pt = case.real(phase).requires_grad_(True)
+    dt = case.real(dal).requires_grad_(True)
+    st = st.requires_grad_(True)
+    img = T.tffr_image(case.plan, st, pt, dt)
+    loss = T.image_entropy(case.plan, img)
+    loss.backward()
+    ref_img = OP.image(case.prob, s, case.rounded(phase), case.rounded(dal))
+    assert abs(float(loss) - OE.entropy(ref_img)) < 1e-5 * abs(OE.entropy(ref_img))
+    gI = OE.entropy_grad(ref_img)
+    rgs, rgph, rgda = OP.backward(case.prob, gI, s, case.rounded(phase), case.rounded(dal))
+    assert rel_l2(st.grad.cpu().numpy(), rgs) < 1e-4
+    assert np.max(np.abs(pt.grad.cpu().numpy() - rgph)) < 1e-4 * np.max(np.abs(rgph))
+    assert np.max(np.abs(dt.grad.cpu().numpy() - rgda)) < 1e-4 * np.max(np.abs(rgda))
+    # a global phase leaves |I| unchanged
+    assert abs(float(pt.grad.double().sum())) < 1e-4 * float(pt.grad.double().abs().sum())
+
+
+def test_entropy_kernel_values():
+    case = Case(4, 8, 64, seed=16)
+    I = case.image_np()
+    It = torch.as_tensor(I, dtype=case.ctype, device=DEV)
+    loss, grad = case.plan.tffr_entropy(It)
+    Ir = It.cpu().numpy().astype(np.complex128)
+    assert abs(float(loss) - OE.entropy(Ir)) < 1e-6
+    assert rel_l2(grad.cpu().numpy(), OE.entropy_grad(Ir)) < 1e-5
+
+
+def test_fp16_samples():
+    case = Case(64, 128, 128, dtype=T.C64_FP16IN, seed=17)
+    s16, st = case.samples()
+    got = case.plan.tffr_forward(st).cpu().numpy()
+    ref = OP.image(case.prob, s16)  # oracle on the FP16-rounded samples
+    assert rel_l2(got, ref) < 1e-5
+
+
+# ---------------------------------------------------------------- edge cases
+def test_single_frequency_and_single_pulse():
+    for size in [(1, 40, 32), (7, 1, 32)]:
+        case = Case(*size, weighting=T.W_QUAD, seed=18)
+        s, st = case.samples()
+        got = case.plan.tffr_forward(st).cpu().numpy()
+        ref = OP.image(case.prob, s)
+        assert rel_l2(got, ref) < 1e-5
+
+
+def test_everything_thresholded_gives_zero_image():
+    case = Case(8, 64, 32, tau=5.0, seed=19)
+    s, st = case.samples()
+    assert case.plan.tffr_kept_count() == 0
+    img = case.plan.tffr_forward(st)
+    assert float(img.abs().max()) == 0.0
+
+
+def test_nonsquare_image():
+    case = Case(40, 90, 48, my=80, fov=40.0, fov_y=25.0, seed=20)
+    s, st = case.samples()
+    got = case.plan.tffr_forward(st).cpu().numpy()
+    assert got.shape == (48, 80)
+    assert rel_l2(got, OP.image(case.prob, s)) < 1e-5
