@@ -21,7 +21,8 @@ namespace {
 constexpr double kPi = 3.141592653589793;
 constexpr int kMaxLogN = 14;
 constexpr int kMaxHalfBand = 16;
-constexpr int kPartials = 1024;  // reduction blocks for entropy / kept count
+constexpr int kPartials = 1024;  // reduction blocks for the kept count
+constexpr int kEntropyParts = 256;  // reduction blocks for the entropy
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -96,6 +97,22 @@ std::vector<double> deapod_table(int m, int nfine, int W, double beta) {
   return out;
 }
 
+// Two-level twiddle table of length-n transforms: [hi: exp(2 pi i 64 j / n), j < n/64]
+// followed by [lo: exp(2 pi i l / n), l < 64], interleaved (re, im).
+std::vector<double> twiddle_table(int n) {
+  const int nh = n / 64;
+  std::vector<double> tw(2 * (size_t)(nh + 64));
+  for (int j = 0; j < nh; ++j) {
+    tw[2 * j] = std::cos(2.0 * kPi * ((double)(64 * j) / n));
+    tw[2 * j + 1] = std::sin(2.0 * kPi * ((double)(64 * j) / n));
+  }
+  for (int l = 0; l < 64; ++l) {
+    tw[2 * (nh + l)] = std::cos(2.0 * kPi * ((double)l / n));
+    tw[2 * (nh + l) + 1] = std::sin(2.0 * kPi * ((double)l / n));
+  }
+  return tw;
+}
+
 int log2_pow2_at_least(double v) {
   int l = 0;
   while ((double)(1 << l) < v - 1e-9) ++l;
@@ -120,7 +137,7 @@ struct tffr_plan {
   int ffr_halfband = 0;
   double beta = 0.0;
   // device tables
-  DevBuf k, ku, ky, ystart, ytap, deapx, deapy, twx, twy, poly, ffr_d;
+  DevBuf k, ku, ky, ystart, ytap, deapx, deapy, twx, twy, poly, ffr_d, ycptr, ycn, ycw;
   // workspace layout
   size_t off_hx = 0, off_part = 0, off_kept = 0, off_count = 0, off_status = 0, off_gband = 0, off_zband = 0,
          off_dband = 0, work_bytes = 0;
@@ -158,6 +175,9 @@ tffr::Tab<R> tables(const tffr_plan* P) {
   t.twx = (const cplx<R>*)P->twx.p;
   t.twy = (const cplx<R>*)P->twy.p;
   t.poly = (const float*)P->poly.p;
+  t.ycell_ptr = (const int32_t*)P->ycptr.p;
+  t.ycell_n = (const int32_t*)P->ycn.p;
+  t.ycell_w = (const R*)P->ycw.p;
   return t;
 }
 
@@ -285,6 +305,37 @@ tffr_status do_adjoint(tffr_plan* P, const void* cot, const void* smp, const voi
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+// Range gridding schedule (see k_fwd_rows): S = samples a thread owns so that samples S
+// apart are more than W fine cells apart, and the part length so that no part of a
+// slice spans the fine row (after wrapping, two samples of a part never share cells).
+void range_schedule(const tffr_params* p, const double* k, const double* ku, int nfx, int* S, int* part_len) {
+  const double tx = p->fov_x / (2.0 * kPi * p->mx);
+  const int P = p->n_freq, W = p->kernel_width;
+  double smin = 1e300;
+  int Q = 1;
+  std::vector<double> U(P);
+  for (int n = 0; n < p->n_pulses; ++n) {
+    for (int i = 0; i < P; ++i) U[i] = std::sqrt(4.0 * (k[i] * k[i]) - ku[n] * ku[n]) * tx * nfx;
+    for (int i = 0; i + 1 < P; ++i) smin = std::min(smin, U[i + 1] - U[i]);
+    for (;; ++Q) {
+      const int len = (P + Q - 1) / Q;
+      bool ok = true;
+      for (int a = 0; a < P && ok; a += len) {
+        const int b = std::min(a + len, P) - 1;
+        ok = (U[b] - U[a] + W + 2.0) <= (double)nfx;
+      }
+      if (ok) break;
+    }
+  }
+  int s = 1;
+  if (P > 1) {
+    const double sm = smin * (1.0 - 1e-9);
+    s = (int)std::min<double>((double)P, std::floor(W / sm) + 1.0);
+  }
+  *S = std::max(1, s);
+  *part_len = (P + Q - 1) / Q;
+}
+
 }  // namespace
 
 // ============================================================================ C ABI
@@ -361,16 +412,20 @@ tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double
   P->beta = 2.30 * W * (1.0 - 1.0 / (2.0 * sig)) / 0.75;
   const size_t csz = P->csize();
   const size_t lds_max = tffr::max_dynamic_lds();
-  if (((size_t)nfx * csz) + (p->weighting == TFFR_W_FFR ? (size_t)p->n_freq * csz : 0) > lds_max ||
-      (size_t)nfy * csz > lds_max)
+  const size_t twx_n = nfx / 64 + 64, twy_n = nfy / 64 + 64;
+  if ((nfx + twx_n) * csz + (p->weighting == TFFR_W_FFR ? (size_t)p->n_freq * csz : 0) > lds_max ||
+      (nfy + twy_n) * csz > lds_max || (nfy + (size_t)p->n_pulses + twy_n) * csz > lds_max)
     return fail(TFFR_ERR_UNSUPPORTED);
-  // range columns per workgroup in the azimuth stage: fill <= 64 KB of LDS but keep
-  // at least ~512 workgroups in flight
-  int cb = (int)std::max<size_t>(1, std::min<size_t>(8, 65536 / ((size_t)nfy * csz)));
+  // range columns per workgroup in the azimuth stage: keep the forward kernel's LDS
+  // (columns + staged spectra + twiddles) within 64 KB where possible, and at least
+  // ~512 workgroups in flight
+  auto cols_lds = [&](int c) { return ((size_t)nfy + p->n_pulses) * c * csz + twy_n * csz; };
+  int cb = 8;
+  while (cb > 1 && cols_lds(cb) > 65536) cb >>= 1;
   while (cb > 1 && (p->mx + cb - 1) / cb < 512) cb >>= 1;
   if (const char* e = std::getenv("TFFR_AZ_COLS")) {
     const int v = std::atoi(e);
-    if (v >= 1 && v <= 16 && (size_t)v * nfy * csz <= lds_max) cb = v;
+    if (v >= 1 && v <= 16 && cols_lds(v) <= lds_max) cb = v;
   }
   P->cb = cb;
 
@@ -412,18 +467,28 @@ tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double
     ys[n] = (int32_t)ui + k0;
     for (int i = 0; i < W; ++i) taps[(size_t)n * W + i] = es((k0 + i - f) / (W / 2.0), P->beta);
   }
+  // azimuth cell table: for every fine azimuth cell, the (slice, tap) pairs that reach it
+  std::vector<int32_t> cptr(nfy + 1, 0), cn((size_t)p->n_pulses * W);
+  std::vector<double> cw((size_t)p->n_pulses * W);
+  for (int n = 0; n < p->n_pulses; ++n)
+    for (int i = 0; i < W; ++i) cptr[(((ys[n] + i) % nfy) + nfy) % nfy + 1]++;
+  for (int c = 0; c < nfy; ++c) cptr[c + 1] += cptr[c];
+  {
+    std::vector<int32_t> fill(cptr.begin(), cptr.end() - 1);
+    for (int n = 0; n < p->n_pulses; ++n)
+      for (int i = 0; i < W; ++i) {
+        const int cell = (((ys[n] + i) % nfy) + nfy) % nfy;
+        cn[fill[cell]] = n;
+        cw[fill[cell]] = taps[(size_t)n * W + i];
+        fill[cell]++;
+      }
+  }
+  range_schedule(p, k, ku, nfx, &g.sub, &g.part_len);
   std::vector<double> dx = deapod_table(p->mx, nfx, W, P->beta), dy = deapod_table(p->my, nfy, W, P->beta);
-  auto twiddles = [](int n) {
-    std::vector<double> tw(2 * (size_t)n);
-    for (int m = 0; m < n; ++m) {
-      tw[2 * m] = std::cos(2.0 * kPi * ((double)m / n));
-      tw[2 * m + 1] = std::sin(2.0 * kPi * ((double)m / n));
-    }
-    return tw;
-  };
-  std::vector<double> twx = twiddles(nfx), twy = twiddles(nfy);
+  std::vector<double> twx = twiddle_table(nfx), twy = twiddle_table(nfy);
   if (P->dbl()) {
     s = upload(P->ky, kuv);
+    if (s == TFFR_OK) s = upload(P->ycw, cw);
     if (s == TFFR_OK) s = upload(P->ytap, taps);
     if (s == TFFR_OK) s = upload(P->deapx, dx);
     if (s == TFFR_OK) s = upload(P->deapy, dy);
@@ -431,6 +496,7 @@ tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double
     if (s == TFFR_OK) s = upload(P->twy, twy);
   } else {
     s = upload(P->ky, cast<float>(kuv));
+    if (s == TFFR_OK) s = upload(P->ycw, cast<float>(cw));
     if (s == TFFR_OK) s = upload(P->ytap, cast<float>(taps));
     if (s == TFFR_OK) s = upload(P->deapx, cast<float>(dx));
     if (s == TFFR_OK) s = upload(P->deapy, cast<float>(dy));
@@ -440,6 +506,8 @@ tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double
   if (s == TFFR_OK) s = upload(P->k, kv);
   if (s == TFFR_OK) s = upload(P->ku, kuv);
   if (s == TFFR_OK) s = upload(P->ystart, ys);
+  if (s == TFFR_OK) s = upload(P->ycptr, cptr);
+  if (s == TFFR_OK) s = upload(P->ycn, cn);
   if (s != TFFR_OK) return fail(s);
 
   // tFFR weight polynomial (float path, integer q only: the tap set is then constant on (0, 1))
@@ -545,7 +613,7 @@ tffr_status tffr_entropy(tffr_plan* P, const void* img, double* loss, void* grad
   hipStream_t st = (hipStream_t)stream;
   double* part = (double*)((char*)work + P->off_part);
   const size_t count = (size_t)P->prm.mx * P->prm.my;
-  const int nparts = (int)std::max<size_t>(1, std::min<size_t>(kPartials, (count + 1023) / 1024));
+  const int nparts = (int)std::max<size_t>(1, std::min<size_t>(kEntropyParts, (count + 1023) / 1024));
   hipError_t e = P->dbl() ? tffr::launch_entropy<double>(P->geo, (const cplx<double>*)img, part, nparts, loss,
                                                          (cplx<double>*)grad, st)
                           : tffr::launch_entropy<float>(P->geo, (const cplx<float>*)img, part, nparts, loss,
@@ -595,14 +663,11 @@ tffr_status tffr_debug_fft(int32_t log2n, int32_t batch, int32_t sign, int32_t d
   if (log2n < 6 || log2n > kMaxLogN || batch < 1 || (sign != 1 && sign != -1) || !in || !out) return TFFR_ERR_ARG;
   if (dtype != TFFR_C64 && dtype != TFFR_C128) return TFFR_ERR_UNSUPPORTED;
   const size_t csz = dtype == TFFR_C128 ? 16 : 8;
-  if (((size_t)csz << log2n) > tffr::max_dynamic_lds()) return TFFR_ERR_UNSUPPORTED;
+  if (csz * (((size_t)1 << log2n) + ((size_t)1 << log2n) / 64 + 64) > tffr::max_dynamic_lds())
+    return TFFR_ERR_UNSUPPORTED;
   const int n = 1 << log2n;
   hipStream_t st = (hipStream_t)stream;
-  std::vector<double> tw(2 * (size_t)n);
-  for (int m = 0; m < n; ++m) {
-    tw[2 * m] = std::cos(2.0 * kPi * ((double)m / n));
-    tw[2 * m + 1] = std::sin(2.0 * kPi * ((double)m / n));
-  }
+  std::vector<double> tw = twiddle_table(n);
   DevBuf dtw;
   tffr_status s = dtype == TFFR_C128 ? upload(dtw, tw) : upload(dtw, cast<float>(tw));
   if (s != TFFR_OK) return s;

@@ -24,6 +24,8 @@ struct Geo {
   int32_t W;                         // gridding kernel width (taps)
   int32_t weighting, thresh_mode, band_r, band_b;
   int32_t use_poly, nseg, deg;  // tFFR weight polynomial (float path)
+  int32_t sub;                  // range gridding: samples per thread per sub-pass group
+  int32_t part_len;             // range gridding: samples per part (part span < fine row)
   int32_t keep0;                // threshold decision for a sample exactly on the lattice
   double beta;                  // ES kernel shape
   double tx_scale;              // kx -> cycles per range pixel: fov_x / (2 pi mx)
@@ -44,8 +46,11 @@ struct Tab {
   const R* ytap;          // [n_pulses][W] azimuth kernel taps of the slice
   const R* deapx;         // [mx] 1 / kernel transform, range
   const R* deapy;         // [my] 1 / kernel transform, azimuth
-  const cplx<R>* twx;     // [nfx] exp(+2 pi i m / nfx)
-  const cplx<R>* twy;     // [nfy] exp(+2 pi i m / nfy)
+  const cplx<R>* twx;     // [nfx/64 + 64] two-level table of exp(+2 pi i m / nfx)
+  const cplx<R>* twy;     // [nfy/64 + 64] two-level table of exp(+2 pi i m / nfy)
+  const int32_t* ycell_ptr;  // [nfy + 1] azimuth cell -> range of (slice, tap) entries
+  const int32_t* ycell_n;    // [n_pulses * W] slice of each entry
+  const R* ycell_w;          // [n_pulses * W] kernel tap of each entry
   const float* poly;      // [nseg][deg+1] tFFR weight polynomial (float path), or null
 };
 

@@ -46,12 +46,6 @@ __device__ __forceinline__ cplx<R> mul_si(cplx<R> a) {  // a * (SIGN i)
   return SIGN > 0 ? cplx<R>{-a.y, a.x} : cplx<R>{a.y, -a.x};
 }
 
-template <typename R>
-__device__ __forceinline__ void lds_add(cplx<R>* p, cplx<R> v) {
-  atomicAdd(&p->x, v.x);
-  atomicAdd(&p->y, v.y);
-}
-
 // ----------------------------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -116,11 +110,27 @@ __device__ __forceinline__ void dft(cplx<R>* a) {
   else dft2<SIGN>(a);
 }
 
+// Twiddle exp(+2 pi i m / N) from the two-level LDS table tw = [hi (N/64)] [lo (64)]:
+// exp(2 pi i m / N) = hi[m / 64] * lo[m % 64].
+template <int N, typename R>
+__device__ __forceinline__ cplx<R> twiddle(const cplx<R>* tw, int m) {
+  return cmul(tw[m >> 6], tw[N / 64 + (m & 63)]);
+}
+template <int N>
+constexpr int tw_entries() {
+  return N / 64 + 64;
+}
+// Copy the two-level twiddle table of length-N transforms into LDS (caller barriers).
+template <int N, int NT, typename R>
+__device__ __forceinline__ void load_twiddles(cplx<R>* tw, const cplx<R>* __restrict__ g) {
+  for (int i = threadIdx.x; i < tw_entries<N>(); i += NT) tw[i] = g[i];
+}
+
 // One Stockham autosort stage of radix RAD after spans P (in place: all reads, barrier,
 // all writes, barrier).  Butterfly i reads x[i + r N/RAD], applies the twiddles
 // exp(SIGN 2 pi i r k / (P RAD)) with k = i mod P, and writes y[(i - k) RAD + k + r P].
 template <int SIGN, int N, int RAD, int P, int NT, typename R>
-__device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* __restrict__ tw) {
+__device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* tw) {
   constexpr int NB = N / RAD;
   constexpr int BPT = (NB + NT - 1) / NT;
   cplx<R> v[BPT][RAD];
@@ -142,7 +152,7 @@ __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* __restric
         constexpr int STEP = N / (P * RAD);
 #pragma unroll
         for (int r = 1; r < RAD; ++r) {
-          cplx<R> w = tw[r * k * STEP];
+          cplx<R> w = twiddle<N>(tw, r * k * STEP);
           if (SIGN < 0) w.y = -w.y;
           v[b][r] = cmul(v[b][r], w);
         }
@@ -157,7 +167,7 @@ __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* __restric
 }
 
 template <int SIGN, int N, int P, int NT, typename R>
-__device__ __forceinline__ void fft_from(cplx<R>* buf, const cplx<R>* __restrict__ tw) {
+__device__ __forceinline__ void fft_from(cplx<R>* buf, const cplx<R>* tw) {
   if constexpr (P < N) {
     constexpr int RAD = (N / P) >= 8 ? 8 : (N / P);
     fft_stage<SIGN, N, RAD, P, NT>(buf, tw);
@@ -165,10 +175,10 @@ __device__ __forceinline__ void fft_from(cplx<R>* buf, const cplx<R>* __restrict
   }
 }
 
-// out[j] = sum_g buf[g] exp(SIGN 2 pi i g j / N), in place in LDS, natural order.
-// Call with all NT threads; the caller must barrier before (writes to buf are read).
+// out[j] = sum_g buf[g] exp(SIGN 2 pi i g j / N), in place in LDS, natural order; tw is
+// the LDS twiddle table.  Call with all NT threads after a barrier.
 template <int SIGN, int N, int NT, typename R>
-__device__ __forceinline__ void lds_fft(cplx<R>* buf, const cplx<R>* __restrict__ tw) {
+__device__ __forceinline__ void lds_fft(cplx<R>* buf, const cplx<R>* tw) {
   fft_from<SIGN, N, 1, NT>(buf, tw);
 }
 
@@ -323,41 +333,81 @@ __device__ __forceinline__ cplx<R> weighted_sample(const Geo& g, const Tab<R>& t
 }
 
 // ============================================================================ forward
+constexpr int SMAX = 16;  // samples a thread holds in registers per sub-pass group
+
 // Range stage: one azimuth slice per workgroup.  Spread the slice's weighted samples
-// onto the periodic fine row (LDS atomics), inverse FFT, keep the centred mx bins and
-// divide by the kernel transform.  stage 0 dumps the gridded row instead.
+// onto the periodic fine row, inverse FFT, keep the centred mx bins and divide by the
+// kernel transform.  stage 0 dumps the gridded row instead.
+//
+// No atomics: kx grows along a slice, so thread t owning the S consecutive samples
+// [b0 + S t, b0 + S t + S) and processing one of them per sub-pass touches cell ranges
+// that are disjoint from every other thread's in that sub-pass (the plan picks S with
+// S * (smallest sample spacing) > W).  The slice is cut into parts whose span is less
+// than the fine row, so no two samples of a part meet after wrapping.  Each sub-pass
+// is a plain read-add-write into LDS followed by a barrier.
 template <typename R, int LOGN, int NT>
 __global__ __launch_bounds__(NT) void k_fwd_rows(Geo g, Tab<R> t, int stype, const void* __restrict__ samples,
                                                  const R* __restrict__ phase, const R* __restrict__ dalong,
                                                  const R* __restrict__ w, cplx<R>* __restrict__ out, int stage) {
   constexpr int N = 1 << LOGN;
   extern __shared__ __align__(16) unsigned char smem[];
-  cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem);
+  cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
+  cplx<R>* buf = tw + tw_entries<N>();
   const int n = blockIdx.x;
+  load_twiddles<N, NT>(tw, t.twx);
   for (int i = threadIdx.x; i < N; i += NT) buf[i] = {0, 0};
   const cplx<R> rot = row_rotation(t, phase, dalong, n);
   const double ku = t.ku[n];
   const R halfw = (R)(0.5 * g.W), inv_halfw = (R)(2.0 / g.W), beta = (R)g.beta;
+  const int S = g.sub, W = g.W;
   __syncthreads();
-  for (int p = threadIdx.x; p < g.n_freq; p += NT) {
-    const double kx = stolt_kx(t.k[p], ku);
-    const double lam = lattice_coord(kx, g.fov_x);
-    const cplx<R> c = weighted_sample<R>(g, t, stype, samples, w, n, p, ku, lam, rot);
-    int ui;
-    R f;
-    fine_pos<R>(kx * g.tx_scale, N, ui, f);
-    const int k0 = (int)ceil(f - halfw);
-    for (int i = 0; i < g.W; ++i) {
-      const R phi = es_kernel((R)(k0 + i) * inv_halfw - f * inv_halfw, beta);
-      lds_add(&buf[(ui + k0 + i) & (N - 1)], phi * c);
+  for (int pa = 0; pa < g.n_freq; pa += g.part_len) {
+    const int pb = min(pa + g.part_len, g.n_freq);
+    for (int b0 = pa; b0 < pb; b0 += S * NT) {
+      const int pt = b0 + S * (int)threadIdx.x;
+      for (int r0 = 0; r0 < S; r0 += SMAX) {
+        cplx<R> c[SMAX];
+        int cell[SMAX];
+        R z0[SMAX];
+#pragma unroll
+        for (int j = 0; j < SMAX; ++j) {
+          const int p = pt + r0 + j;
+          cell[j] = 0;
+          z0[j] = 0;
+          c[j] = {0, 0};
+          if (r0 + j < S && p < pb) {
+            const double kx = stolt_kx(t.k[p], ku);
+            const double lam = lattice_coord(kx, g.fov_x);
+            c[j] = weighted_sample<R>(g, t, stype, samples, w, n, p, ku, lam, rot);
+            int ui;
+            R f;
+            fine_pos<R>(kx * g.tx_scale, N, ui, f);
+            const int k0 = (int)ceil(f - halfw);
+            cell[j] = ui + k0;
+            z0[j] = ((R)k0 - f) * inv_halfw;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < SMAX; ++j) {
+          if (r0 + j < S) {
+            if (pt + r0 + j < pb) {
+              for (int i = 0; i < W; ++i) {
+                const R phi = es_kernel(z0[j] + (R)i * inv_halfw, beta);
+                cplx<R>& b = buf[(cell[j] + i) & (N - 1)];
+                b = b + phi * c[j];
+              }
+            }
+            __syncthreads();
+          }
+        }
+      }
     }
   }
-  __syncthreads();
   if (stage == 0) {
     for (int i = threadIdx.x; i < N; i += NT) out[(size_t)n * N + i] = buf[i];
     return;
   }
-  lds_fft<+1, N, NT>(buf, t.twx);
+  lds_fft<+1, N, NT>(buf, tw);
   const int mx = g.mx;
   for (int jx = threadIdx.x; jx < mx; jx += NT) {
     const cplx<R> v = buf[(jx - mx / 2) & (N - 1)];
@@ -365,32 +415,37 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(Geo g, Tab<R> t, int stype, con
   }
 }
 
-// Azimuth stage: CB range columns per workgroup.  Spread every slice's range spectrum
-// value at the slice's azimuth position (taps precomputed per slice), inverse FFT along
-// azimuth, keep the centred my bins, divide by the kernel transform, write the image
-// columns (range-major, contiguous).
+// Azimuth stage: CB range columns per workgroup.  The block's columns of the range
+// spectra are staged in LDS; every fine azimuth cell then gathers its (slice, tap) pairs
+// from the plan's cell table (no atomics), inverse FFT along azimuth, keep the centred
+// my bins, divide by the kernel transform, write the image columns (range-major).
 template <typename R, int LOGN, int NT>
 __global__ __launch_bounds__(NT) void k_fwd_cols(Geo g, Tab<R> t, int cb, const cplx<R>* __restrict__ hx,
                                                  cplx<R>* __restrict__ img) {
   constexpr int N = 1 << LOGN;
   extern __shared__ __align__(16) unsigned char smem[];
-  cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem);
+  cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
+  cplx<R>* buf = tw + tw_entries<N>();
+  cplx<R>* hs = buf + (size_t)cb * N;  // [n_pulses][cb]
   const int c0 = blockIdx.x * cb;
   const int ncol = min(cb, g.mx - c0);
-  for (int i = threadIdx.x; i < cb * N; i += NT) buf[i] = {0, 0};
-  __syncthreads();
-  const int W = g.W;
+  load_twiddles<N, NT>(tw, t.twy);
   const int total = g.n_pulses * ncol;
   for (int idx = threadIdx.x; idx < total; idx += NT) {
-    const int n = idx / ncol, c = idx - n * ncol;
-    const cplx<R> v = hx[(size_t)n * g.mx + c0 + c];
-    const int ys = t.ystart[n];
-    const R* tap = t.ytap + (size_t)n * W;
-    cplx<R>* col = buf + c * N;
-    for (int i = 0; i < W; ++i) lds_add(&col[(ys + i) & (N - 1)], tap[i] * v);
+    const int nn = idx / ncol, c = idx - nn * ncol;
+    hs[nn * cb + c] = hx[(size_t)nn * g.mx + c0 + c];
   }
   __syncthreads();
-  for (int c = 0; c < ncol; ++c) lds_fft<+1, N, NT>(buf + c * N, t.twy);
+  for (int c = 0; c < ncol; ++c) {
+    for (int iy = threadIdx.x; iy < N; iy += NT) {
+      const int e0 = t.ycell_ptr[iy], e1 = t.ycell_ptr[iy + 1];
+      cplx<R> acc = {0, 0};
+      for (int e = e0; e < e1; ++e) acc = acc + t.ycell_w[e] * hs[t.ycell_n[e] * cb + c];
+      buf[c * N + iy] = acc;
+    }
+  }
+  __syncthreads();
+  for (int c = 0; c < ncol; ++c) lds_fft<+1, N, NT>(buf + c * N, tw);
   const int my = g.my;
   for (int c = 0; c < ncol; ++c) {
     const cplx<R>* col = buf + c * N;
@@ -407,10 +462,12 @@ __global__ __launch_bounds__(NT) void k_adj_cols(Geo g, Tab<R> t, int cb, const 
                                                  cplx<R>* __restrict__ hx) {
   constexpr int N = 1 << LOGN;
   extern __shared__ __align__(16) unsigned char smem[];
-  cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem);
+  cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
+  cplx<R>* buf = tw + tw_entries<N>();
   const int c0 = blockIdx.x * cb;
   const int ncol = min(cb, g.mx - c0);
   const int my = g.my;
+  load_twiddles<N, NT>(tw, t.twy);
   for (int c = 0; c < ncol; ++c) {
     const cplx<R>* in = cot + (size_t)(c0 + c) * my;
     for (int i = threadIdx.x; i < N; i += NT) {
@@ -420,7 +477,7 @@ __global__ __launch_bounds__(NT) void k_adj_cols(Geo g, Tab<R> t, int cb, const 
     }
   }
   __syncthreads();
-  for (int c = 0; c < ncol; ++c) lds_fft<-1, N, NT>(buf + c * N, t.twy);
+  for (int c = 0; c < ncol; ++c) lds_fft<-1, N, NT>(buf + c * N, tw);
   const int W = g.W;
   const int total = g.n_pulses * ncol;
   for (int idx = threadIdx.x; idx < total; idx += NT) {
@@ -445,9 +502,11 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
                                                  R* __restrict__ grad_dalong) {
   constexpr int N = 1 << LOGN;
   extern __shared__ __align__(16) unsigned char smem[];
-  cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem);
+  cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
+  cplx<R>* buf = tw + tw_entries<N>();
   cplx<R>* gbuf = buf + N;  // FFR only: interpolated values of the slice
   const int n = blockIdx.x;
+  load_twiddles<N, NT>(tw, t.twx);
   const int mx = g.mx;
   const cplx<R>* in = hx + (size_t)n * mx;
   for (int i = threadIdx.x; i < N; i += NT) {
@@ -456,7 +515,7 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
     buf[i] = (jx >= 0 && jx < mx) ? t.deapx[jx] * in[jx] : cplx<R>{0, 0};
   }
   __syncthreads();
-  lds_fft<-1, N, NT>(buf, t.twx);
+  lds_fft<-1, N, NT>(buf, tw);
   const cplx<R> rot = row_rotation(t, phase, dalong, n);
   const double ku = t.ku[n];
   const R halfw = (R)(0.5 * g.W), inv_halfw = (R)(2.0 / g.W), beta = (R)g.beta;
@@ -675,11 +734,13 @@ template <typename R, int SIGN, int LOGN, int NT>
 __global__ __launch_bounds__(NT) void k_fft(const cplx<R>* __restrict__ in, cplx<R>* out, const cplx<R>* __restrict__ tw) {
   constexpr int N = 1 << LOGN;
   extern __shared__ __align__(16) unsigned char smem[];
-  cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem);
+  cplx<R>* twl = reinterpret_cast<cplx<R>*>(smem);
+  cplx<R>* buf = twl + tw_entries<N>();
   const size_t off = (size_t)blockIdx.x * N;
+  load_twiddles<N, NT>(twl, tw);
   for (int i = threadIdx.x; i < N; i += NT) buf[i] = in[off + i];
   __syncthreads();
-  lds_fft<SIGN, N, NT>(buf, tw);
+  lds_fft<SIGN, N, NT>(buf, twl);
   for (int i = threadIdx.x; i < N; i += NT) out[off + i] = buf[i];
 }
 
@@ -727,7 +788,7 @@ size_t max_dynamic_lds() {
 template <typename R>
 hipError_t launch_fwd_rows(const Geo& g, const Tab<R>& t, int stype, const void* samples, const R* phase,
                            const R* dalong, const R* w, cplx<R>* out, int stage, hipStream_t st) {
-  const size_t lds = sizeof(cplx<R>) << g.lognfx;
+  const size_t lds = sizeof(cplx<R>) * (((size_t)1 << g.lognfx) + ((size_t)1 << g.lognfx) / 64 + 64);
   TFFR_LOGN_DISPATCH(g.lognfx, {
     constexpr int NT = nt_for<L>();
     auto fn = k_fwd_rows<R, L, NT>;
@@ -740,7 +801,8 @@ hipError_t launch_fwd_rows(const Geo& g, const Tab<R>& t, int stype, const void*
 
 template <typename R>
 hipError_t launch_fwd_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>* hx, cplx<R>* img, hipStream_t st) {
-  const size_t lds = (sizeof(cplx<R>) << g.lognfy) * cb;
+  const size_t lds = sizeof(cplx<R>) * ((((size_t)1 << g.lognfy) + g.n_pulses) * cb +
+                                         ((size_t)1 << g.lognfy) / 64 + 64);
   const int grid = (g.mx + cb - 1) / cb;
   TFFR_LOGN_DISPATCH(g.lognfy, {
     constexpr int NT = nt_for<L>();
@@ -754,7 +816,7 @@ hipError_t launch_fwd_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>*
 
 template <typename R>
 hipError_t launch_adj_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>* cot, cplx<R>* hx, hipStream_t st) {
-  const size_t lds = (sizeof(cplx<R>) << g.lognfy) * cb;
+  const size_t lds = sizeof(cplx<R>) * (((size_t)1 << g.lognfy) * cb + ((size_t)1 << g.lognfy) / 64 + 64);
   const int grid = (g.mx + cb - 1) / cb;
   TFFR_LOGN_DISPATCH(g.lognfy, {
     constexpr int NT = nt_for<L>();
@@ -770,7 +832,7 @@ template <typename R>
 hipError_t launch_adj_rows(const Geo& g, const Tab<R>& t, int stype, const cplx<R>* hx, const void* samples,
                            const R* phase, const R* dalong, const R* w, cplx<R>* grad_s, R* grad_phase,
                            R* grad_dalong, hipStream_t st) {
-  size_t lds = sizeof(cplx<R>) << g.lognfx;
+  size_t lds = sizeof(cplx<R>) * (((size_t)1 << g.lognfx) + ((size_t)1 << g.lognfx) / 64 + 64);
   if (g.weighting == 2) lds += sizeof(cplx<R>) * (size_t)g.n_freq;
   TFFR_LOGN_DISPATCH(g.lognfx, {
     constexpr int NT = nt_for<L>();
@@ -824,7 +886,7 @@ hipError_t launch_entropy(const Geo& g, const cplx<R>* img, double* partials, in
 template <typename R>
 hipError_t launch_fft(int log2n, int batch, int sign, const cplx<R>* in, cplx<R>* out, const cplx<R>* tw,
                       hipStream_t st) {
-  const size_t lds = sizeof(cplx<R>) << log2n;
+  const size_t lds = sizeof(cplx<R>) * (((size_t)1 << log2n) + ((size_t)1 << log2n) / 64 + 64);
   TFFR_LOGN_DISPATCH(log2n, {
     constexpr int NT = nt_for<L>();
     if (sign > 0) {

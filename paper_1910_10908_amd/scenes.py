@@ -138,14 +138,14 @@ def _phase_history_clutter(kxx, kut, fov, rng, device, sigma2=0.01, spacing=1.0)
     pt = torch.as_tensor(pos, dtype=torch.float64, device=device)
     Ey = torch.polar(torch.ones(kut.numel(), g, dtype=torch.float64, device=device),
                      -kut[:, None] * pt[None, :])  # [n, gy]
-    V = Ey @ ct.T  # [n, gx]
+    V = Ey @ ct.T.contiguous()  # [n, gx]
     out = torch.zeros(kxx.shape, dtype=torch.complex128, device=device)
     rows = max(1, (1 << 22) // max(1, kxx.shape[1] * g))
     for n0 in range(0, kxx.shape[0], rows):
         n1 = min(n0 + rows, kxx.shape[0])
         ph = kxx[n0:n1, :, None] * pt[None, None, :]  # [rows, p, gx]
         E = torch.polar(torch.ones_like(ph), -ph)
-        out[n0:n1] = torch.einsum("npg,ng->np", E, V[n0:n1])
+        out[n0:n1] = torch.matmul(E, V[n0:n1].unsqueeze(-1).contiguous()).squeeze(-1)
     return out
 
 
