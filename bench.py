@@ -45,10 +45,11 @@ def parse():
 class Step:
     """Buffers and launches of one step for one weighting method."""
 
-    def __init__(self, T, plan, samples, phase, dalong, ffr=False):
+    def __init__(self, T, plan, samples, phase, dalong, ffr=False, fused=True):
         import torch
 
         self.T, self.plan, self.s, self.ph, self.da, self.ffr = T, plan, samples, phase, dalong, ffr
+        self.fused = fused
         dev = samples.device
         self.img = torch.empty(plan.shape_image, dtype=plan.ctype, device=dev)
         self.gI = torch.empty_like(self.img)
@@ -60,19 +61,21 @@ class Step:
         self.gda = torch.empty_like(self.gph)
 
     def __call__(self):
-        import ctypes
-
         T, P = self.T, self.plan
         lib, h, work = P.lib, P.handle, T._ptr(P.work)
         st = T._stream()
         if self.ffr:
             T._lib.check(lib.tffr_weights(h, T._ptr(self.D), work, st))
+        if self.fused:
+            T._lib.check(lib.tffr_entropy_step(h, T._ptr(self.s), T._ptr(self.ph), T._ptr(self.da), T._ptr(self.D),
+                                               T._ptr(self.img), T._ptr(self.loss), T._ptr(self.gs),
+                                               T._ptr(self.gph), T._ptr(self.gda), work, st))
+            return
         T._lib.check(lib.tffr_forward(h, T._ptr(self.s), T._ptr(self.ph), T._ptr(self.da), T._ptr(self.D),
                                       T._ptr(self.img), work, st))
         T._lib.check(lib.tffr_entropy(h, T._ptr(self.img), T._ptr(self.loss), T._ptr(self.gI), work, st))
         T._lib.check(lib.tffr_adjoint(h, T._ptr(self.gI), T._ptr(self.s), T._ptr(self.ph), T._ptr(self.da),
                                       T._ptr(self.D), T._ptr(self.gs), T._ptr(self.gph), T._ptr(self.gda), work, st))
-        del ctypes
 
 
 def time_step(torch, fn, steps, warmup, graph):

@@ -162,6 +162,18 @@ tffr_status tffr_adjoint(tffr_plan *plan, const void *d_grad_image, const void *
 tffr_status tffr_entropy(tffr_plan *plan, const void *d_image, double *d_loss,
                          void *d_grad_image, void *d_work, tffr_stream stream);
 
+/* One autofocus-style step, fused: forward image, image entropy E (as tffr_entropy),
+ * and the adjoint of dE/dI (as tffr_adjoint with grad_image = tffr_entropy's gradient)
+ * without materialising dE/dI: the azimuth forward kernel also reduces the entropy sums
+ * and the first adjoint kernel forms the gradient from the image in registers.
+ *   arguments as in tffr_forward / tffr_adjoint; d_image is written (range-major) and
+ *   d_loss (device double[1]) receives E; d_samples is required; d_grad_phase and
+ *   d_grad_dalong may be NULL. */
+tffr_status tffr_entropy_step(tffr_plan *plan, const void *d_samples, const void *d_phase,
+                              const void *d_dalong, const void *d_user_w, void *d_image,
+                              double *d_loss, void *d_grad_samples, void *d_grad_phase,
+                              void *d_grad_dalong, void *d_work, tffr_stream stream);
+
 const char *tffr_status_string(tffr_status s);
 
 #ifdef __cplusplus

@@ -23,6 +23,7 @@ constexpr int kMaxLogN = 14;
 constexpr int kMaxHalfBand = 16;
 constexpr int kPartials = 1024;  // reduction blocks for the kept count
 constexpr int kEntropyParts = 256;  // reduction blocks for the entropy
+constexpr int kFuseStatsMax = 1024;  // entropy step: adjoint blocks reduce up to this many partials
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -137,9 +138,9 @@ struct tffr_plan {
   int ffr_halfband = 0;
   double beta = 0.0;
   // device tables
-  DevBuf k, ku, ky, ystart, ytap, deapx, deapy, twx, twy, poly, ffr_d, ycptr, ycn, ycw;
+  DevBuf k, ku, ky, ystart, ytap, deapx, deapy, twx, twy, poly, ffr_d, ycn, ycw;
   // workspace layout
-  size_t off_hx = 0, off_part = 0, off_kept = 0, off_count = 0, off_status = 0, off_gband = 0, off_zband = 0,
+  size_t off_hx = 0, off_part = 0, off_stats = 0, off_kept = 0, off_count = 0, off_status = 0, off_gband = 0, off_zband = 0,
          off_dband = 0, work_bytes = 0;
   bool dbl() const { return prm.dtype == TFFR_C128; }
   size_t csize() const { return dbl() ? 16 : 8; }
@@ -175,7 +176,6 @@ tffr::Tab<R> tables(const tffr_plan* P) {
   t.twx = (const cplx<R>*)P->twx.p;
   t.twy = (const cplx<R>*)P->twy.p;
   t.poly = (const float*)P->poly.p;
-  t.ycell_ptr = (const int32_t*)P->ycptr.p;
   t.ycell_n = (const int32_t*)P->ycn.p;
   t.ycell_w = (const R*)P->ycw.p;
   return t;
@@ -285,7 +285,7 @@ tffr_status do_forward(tffr_plan* P, const void* smp, const void* ph, const void
     return hip_status(tffr::launch_fwd_rows<R>(P->geo, t, sample_type(P), smp, (const R*)ph, (const R*)da, w,
                                                (cplx<R>*)img, stage_only, st));
   hipError_t e = tffr::launch_fwd_rows<R>(P->geo, t, sample_type(P), smp, (const R*)ph, (const R*)da, w, hx, 1, st);
-  if (e == hipSuccess) e = tffr::launch_fwd_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, st);
+  if (e == hipSuccess) e = tffr::launch_fwd_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, nullptr, st);
   return hip_status(e);
 }
 
@@ -296,7 +296,32 @@ tffr_status do_adjoint(tffr_plan* P, const void* cot, const void* smp, const voi
   const R* w = (const R*)uw;
   if (!w && P->prm.weighting == TFFR_W_FFR) w = (const R*)P->ffr_d.p;
   cplx<R>* hx = (cplx<R>*)((char*)work + P->off_hx);
-  hipError_t e = tffr::launch_adj_cols<R>(P->geo, t, P->cb, (const cplx<R>*)cot, hx, st);
+  hipError_t e = tffr::launch_adj_cols<R>(P->geo, t, P->cb, (const cplx<R>*)cot, hx, nullptr, nullptr, 0, nullptr, st);
+  if (e == hipSuccess)
+    e = tffr::launch_adj_rows<R>(P->geo, t, sample_type(P), hx, smp, (const R*)ph, (const R*)da, w, (cplx<R>*)gs,
+                                 (R*)gph, (R*)gda, st);
+  return hip_status(e);
+}
+
+template <typename R>
+tffr_status do_entropy_step(tffr_plan* P, const void* smp, const void* ph, const void* da, const void* uw, void* img,
+                            double* loss, void* gs, void* gph, void* gda, void* work, hipStream_t st) {
+  const tffr::Tab<R> t = tables<R>(P);
+  const R* w = (const R*)uw;
+  if (!w && P->prm.weighting == TFFR_W_FFR) w = (const R*)P->ffr_d.p;
+  char* wb = (char*)work;
+  cplx<R>* hx = (cplx<R>*)(wb + P->off_hx);
+  double* part = (double*)(wb + P->off_part);
+  double* stats = (double*)(wb + P->off_stats);
+  const int nparts = (P->prm.mx + P->cb - 1) / P->cb;
+  hipError_t e = tffr::launch_fwd_rows<R>(P->geo, t, sample_type(P), smp, (const R*)ph, (const R*)da, w, hx, 1, st);
+  if (e == hipSuccess) e = tffr::launch_fwd_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, part, st);
+  // few partial sums: every adjoint block reduces them itself (no separate launch)
+  const bool fuse = nparts <= kFuseStatsMax;
+  if (e == hipSuccess && !fuse) e = tffr::launch_entropy_stats(part, nparts, stats, loss, st);
+  if (e == hipSuccess)
+    e = fuse ? tffr::launch_adj_cols<R>(P->geo, t, P->cb, (const cplx<R>*)img, hx, nullptr, part, nparts, loss, st)
+             : tffr::launch_adj_cols<R>(P->geo, t, P->cb, (const cplx<R>*)img, hx, stats, nullptr, 0, nullptr, st);
   if (e == hipSuccess)
     e = tffr::launch_adj_rows<R>(P->geo, t, sample_type(P), hx, smp, (const R*)ph, (const R*)da, w, (cplx<R>*)gs,
                                  (R*)gph, (R*)gda, st);
@@ -413,19 +438,19 @@ tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double
   const size_t csz = P->csize();
   const size_t lds_max = tffr::max_dynamic_lds();
   const size_t twx_n = nfx / 64 + 64, twy_n = nfy / 64 + 64;
-  if ((nfx + twx_n) * csz + (p->weighting == TFFR_W_FFR ? (size_t)p->n_freq * csz : 0) > lds_max ||
+  if ((nfx + twx_n) * csz + 2048 + (p->weighting == TFFR_W_FFR ? (size_t)p->n_freq * csz : 0) > lds_max ||
       (nfy + twy_n) * csz > lds_max || (nfy + (size_t)p->n_pulses + twy_n) * csz > lds_max)
     return fail(TFFR_ERR_UNSUPPORTED);
   // range columns per workgroup in the azimuth stage: keep the forward kernel's LDS
   // (columns + staged spectra + twiddles) within 64 KB where possible, and at least
   // ~512 workgroups in flight
   auto cols_lds = [&](int c) { return ((size_t)nfy + p->n_pulses) * c * csz + twy_n * csz; };
-  int cb = 8;
+  int cb = 4;
   while (cb > 1 && cols_lds(cb) > 65536) cb >>= 1;
   while (cb > 1 && (p->mx + cb - 1) / cb < 512) cb >>= 1;
   if (const char* e = std::getenv("TFFR_AZ_COLS")) {
     const int v = std::atoi(e);
-    if (v >= 1 && v <= 16 && cols_lds(v) <= lds_max) cb = v;
+    if ((v == 1 || v == 2 || v == 4) && cols_lds(v) <= lds_max) cb = v;
   }
   P->cb = cb;
 
@@ -454,6 +479,8 @@ tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double
   g.inv_g0 = g0 != 0.0 ? 1.0 / g0 : 0.0;
   g.keep0 = p->thresh_mode == TFFR_THRESH_LITERAL ? (std::fabs(g.inv_g0) >= p->tau) : (g0 >= p->tau);
   g.near_rel = 1e-5;
+  g.near_f = (float)g.near_rel;
+  g.thr_f = (float)(p->thresh_mode == TFFR_THRESH_LITERAL ? p->tau : 1.0 / p->tau);
 
   std::vector<double> kv(k, k + p->n_freq), kuv(ku, ku + p->n_pulses);
   // per-slice azimuth taps
@@ -467,22 +494,23 @@ tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double
     ys[n] = (int32_t)ui + k0;
     for (int i = 0; i < W; ++i) taps[(size_t)n * W + i] = es((k0 + i - f) / (W / 2.0), P->beta);
   }
-  // azimuth cell table: for every fine azimuth cell, the (slice, tap) pairs that reach it
-  std::vector<int32_t> cptr(nfy + 1, 0), cn((size_t)p->n_pulses * W);
-  std::vector<double> cw((size_t)p->n_pulses * W);
+  // azimuth cell table: for every fine azimuth cell, the (slice, tap) pairs that reach it,
+  // padded to the largest count with (slice 0, tap 0)
+  std::vector<int32_t> ccount(nfy, 0);
   for (int n = 0; n < p->n_pulses; ++n)
-    for (int i = 0; i < W; ++i) cptr[(((ys[n] + i) % nfy) + nfy) % nfy + 1]++;
-  for (int c = 0; c < nfy; ++c) cptr[c + 1] += cptr[c];
-  {
-    std::vector<int32_t> fill(cptr.begin(), cptr.end() - 1);
-    for (int n = 0; n < p->n_pulses; ++n)
-      for (int i = 0; i < W; ++i) {
-        const int cell = (((ys[n] + i) % nfy) + nfy) % nfy;
-        cn[fill[cell]] = n;
-        cw[fill[cell]] = taps[(size_t)n * W + i];
-        fill[cell]++;
-      }
-  }
+    for (int i = 0; i < W; ++i) ccount[(((ys[n] + i) % nfy) + nfy) % nfy]++;
+  const int yemax = std::max(1, *std::max_element(ccount.begin(), ccount.end()));
+  std::vector<int32_t> cn((size_t)nfy * yemax, 0);
+  std::vector<double> cw((size_t)nfy * yemax, 0.0);
+  std::fill(ccount.begin(), ccount.end(), 0);
+  for (int n = 0; n < p->n_pulses; ++n)
+    for (int i = 0; i < W; ++i) {
+      const int cell = (((ys[n] + i) % nfy) + nfy) % nfy;
+      const size_t slot = (size_t)cell * yemax + ccount[cell]++;
+      cn[slot] = n;
+      cw[slot] = taps[(size_t)n * W + i];
+    }
+  g.yemax = yemax;
   range_schedule(p, k, ku, nfx, &g.sub, &g.part_len);
   std::vector<double> dx = deapod_table(p->mx, nfx, W, P->beta), dy = deapod_table(p->my, nfy, W, P->beta);
   std::vector<double> twx = twiddle_table(nfx), twy = twiddle_table(nfy);
@@ -506,7 +534,6 @@ tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double
   if (s == TFFR_OK) s = upload(P->k, kv);
   if (s == TFFR_OK) s = upload(P->ku, kuv);
   if (s == TFFR_OK) s = upload(P->ystart, ys);
-  if (s == TFFR_OK) s = upload(P->ycptr, cptr);
   if (s == TFFR_OK) s = upload(P->ycn, cn);
   if (s != TFFR_OK) return fail(s);
 
@@ -528,7 +555,9 @@ tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double
   P->off_hx = off;
   off = align_up(off + (size_t)p->n_pulses * p->mx * csz);
   P->off_part = off;
-  off = align_up(off + sizeof(double) * 2 * kPartials);
+  off = align_up(off + sizeof(double) * 2 * std::max<size_t>(kEntropyParts, (p->mx + P->cb - 1) / P->cb));
+  P->off_stats = off;
+  off = align_up(off + sizeof(double) * 2);
   P->off_kept = off;
   off = align_up(off + sizeof(unsigned long long) * kPartials);
   P->off_count = off;
@@ -619,6 +648,16 @@ tffr_status tffr_entropy(tffr_plan* P, const void* img, double* loss, void* grad
                           : tffr::launch_entropy<float>(P->geo, (const cplx<float>*)img, part, nparts, loss,
                                                         (cplx<float>*)grad, st);
   return hip_status(e);
+}
+
+tffr_status tffr_entropy_step(tffr_plan* P, const void* smp, const void* ph, const void* da, const void* uw, void* img,
+                              double* loss, void* gs, void* gph, void* gda, void* work, tffr_stream stream) {
+  if (!P || !smp || !img || !loss || !gs || !work) return TFFR_ERR_ARG;
+  if (P->prm.weighting == TFFR_W_USER && !uw) return TFFR_ERR_ARG;
+  if (!aligned(work, 16) || !aligned(img, P->csize() / 2) || !aligned(gs, P->csize() / 2)) return TFFR_ERR_LAYOUT;
+  hipStream_t st = (hipStream_t)stream;
+  return P->dbl() ? do_entropy_step<double>(P, smp, ph, da, uw, img, loss, gs, gph, gda, work, st)
+                  : do_entropy_step<float>(P, smp, ph, da, uw, img, loss, gs, gph, gda, work, st);
 }
 
 tffr_status tffr_weights(tffr_plan* P, void* d_w, void* work, tffr_stream stream) {

@@ -26,6 +26,7 @@ struct Geo {
   int32_t use_poly, nseg, deg;  // tFFR weight polynomial (float path)
   int32_t sub;                  // range gridding: samples per thread per sub-pass group
   int32_t part_len;             // range gridding: samples per part (part span < fine row)
+  int32_t yemax;                // azimuth gridding: most (slice, tap) pairs reaching one cell
   int32_t keep0;                // threshold decision for a sample exactly on the lattice
   double beta;                  // ES kernel shape
   double tx_scale;              // kx -> cycles per range pixel: fov_x / (2 pi mx)
@@ -34,6 +35,8 @@ struct Geo {
   double ema2, epa2;  // exp(-a/2), exp(+a/2)
   double inv_g0;      // 1/g(0) for a sample exactly on the lattice
   double near_rel;    // polynomial weights this close to the threshold are re-decided in FP64
+  float thr_f;        // float threshold on 1/g: tau (literal) or 1/tau (correlation)
+  float near_f;       // near_rel as float
 };
 
 // Small device tables owned by the plan, in the compute type R.
@@ -48,9 +51,8 @@ struct Tab {
   const R* deapy;         // [my] 1 / kernel transform, azimuth
   const cplx<R>* twx;     // [nfx/64 + 64] two-level table of exp(+2 pi i m / nfx)
   const cplx<R>* twy;     // [nfy/64 + 64] two-level table of exp(+2 pi i m / nfy)
-  const int32_t* ycell_ptr;  // [nfy + 1] azimuth cell -> range of (slice, tap) entries
-  const int32_t* ycell_n;    // [n_pulses * W] slice of each entry
-  const R* ycell_w;          // [n_pulses * W] kernel tap of each entry
+  const int32_t* ycell_n;  // [nfy][yemax] slices whose taps reach each azimuth cell (padded with 0)
+  const R* ycell_w;        // [nfy][yemax] the matching kernel taps (padded with 0)
   const float* poly;      // [nseg][deg+1] tFFR weight polynomial (float path), or null
 };
 
@@ -63,10 +65,12 @@ hipError_t launch_fwd_rows(const Geo& g, const Tab<R>& t, int stype, const void*
                            int stage, hipStream_t st);
 template <typename R>
 hipError_t launch_fwd_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>* hx,
-                           cplx<R>* img, hipStream_t st);
+                           cplx<R>* img, double* partials, hipStream_t st);
 template <typename R>
 hipError_t launch_adj_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>* cot,
-                           cplx<R>* hx, hipStream_t st);
+                           cplx<R>* hx, const double* stats, const double* partials, int nparts,
+                           double* loss, hipStream_t st);
+hipError_t launch_entropy_stats(const double* partials, int nparts, double* stats, double* loss, hipStream_t st);
 template <typename R>
 hipError_t launch_adj_rows(const Geo& g, const Tab<R>& t, int stype, const cplx<R>* hx,
                            const void* samples, const R* phase, const R* dalong, const R* w,

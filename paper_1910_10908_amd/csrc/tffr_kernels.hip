@@ -126,27 +126,32 @@ __device__ __forceinline__ void load_twiddles(cplx<R>* tw, const cplx<R>* __rest
   for (int i = threadIdx.x; i < tw_entries<N>(); i += NT) tw[i] = g[i];
 }
 
-// One Stockham autosort stage of radix RAD after spans P (in place: all reads, barrier,
-// all writes, barrier).  Butterfly i reads x[i + r N/RAD], applies the twiddles
-// exp(SIGN 2 pi i r k / (P RAD)) with k = i mod P, and writes y[(i - k) RAD + k + r P].
-template <int SIGN, int N, int RAD, int P, int NT, typename R>
+// One Stockham autosort stage of radix RAD after spans P, on NBAT transforms stored
+// back to back (in place: all reads, barrier, all writes, barrier).  Butterfly i of a
+// transform reads x[i + r N/RAD], applies exp(SIGN 2 pi i r k / (P RAD)) with
+// k = i mod P, and writes y[(i - k) RAD + k + r P].
+template <int SIGN, int N, int RAD, int P, int NT, int NBAT, typename R>
 __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* tw) {
   constexpr int NB = N / RAD;
-  constexpr int BPT = (NB + NT - 1) / NT;
+  constexpr int TOT = NB * NBAT;
+  constexpr int BPT = (TOT + NT - 1) / NT;
   cplx<R> v[BPT][RAD];
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
-    const int i = threadIdx.x + b * NT;
-    if (NB % NT == 0 || i < NB) {
+    const int bf = threadIdx.x + b * NT;
+    if (TOT % NT == 0 || bf < TOT) {
+      const int col = bf / NB, i = bf - col * NB;
+      const cplx<R>* x = buf + col * N;
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) v[b][r] = buf[i + r * NB];
+      for (int r = 0; r < RAD; ++r) v[b][r] = x[i + r * NB];
     }
   }
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
-    const int i = threadIdx.x + b * NT;
-    if (NB % NT == 0 || i < NB) {
+    const int bf = threadIdx.x + b * NT;
+    if (TOT % NT == 0 || bf < TOT) {
+      const int col = bf / NB, i = bf - col * NB;
       const int k = i & (P - 1);
       if constexpr (P > 1) {
         constexpr int STEP = N / (P * RAD);
@@ -159,107 +164,132 @@ __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* tw) {
       }
       dft<SIGN, RAD>(v[b]);
       const int j = (i - k) * RAD + k;
+      cplx<R>* y = buf + col * N;
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) buf[j + r * P] = v[b][r];
+      for (int r = 0; r < RAD; ++r) y[j + r * P] = v[b][r];
     }
   }
   __syncthreads();
 }
 
-template <int SIGN, int N, int P, int NT, typename R>
+template <int SIGN, int N, int P, int NT, int NBAT, typename R>
 __device__ __forceinline__ void fft_from(cplx<R>* buf, const cplx<R>* tw) {
   if constexpr (P < N) {
     constexpr int RAD = (N / P) >= 8 ? 8 : (N / P);
-    fft_stage<SIGN, N, RAD, P, NT>(buf, tw);
-    fft_from<SIGN, N, P * RAD, NT>(buf, tw);
+    fft_stage<SIGN, N, RAD, P, NT, NBAT>(buf, tw);
+    fft_from<SIGN, N, P * RAD, NT, NBAT>(buf, tw);
   }
 }
 
-// out[j] = sum_g buf[g] exp(SIGN 2 pi i g j / N), in place in LDS, natural order; tw is
-// the LDS twiddle table.  Call with all NT threads after a barrier.
-template <int SIGN, int N, int NT, typename R>
+// out[j] = sum_g buf[g] exp(SIGN 2 pi i g j / N) for NBAT transforms stored back to back
+// in LDS, in place, natural order; tw is the LDS twiddle table.  Call with all NT
+// threads after a barrier.
+template <int SIGN, int N, int NT, int NBAT = 1, typename R>
 __device__ __forceinline__ void lds_fft(cplx<R>* buf, const cplx<R>* tw) {
-  fft_from<SIGN, N, 1, NT>(buf, tw);
+  fft_from<SIGN, N, 1, NT, NBAT>(buf, tw);
 }
 
 // ----------------------------------------------------------------------------- geometry
-// Stolt map and lattice coordinate, rounded exactly as written (no contraction), so a
-// threshold decision taken from them matches an FP64 evaluation in the same order.
+// Stolt map (FP64, no contraction) and lattice coordinate lam = kx fov_x / (2 pi),
+// formed as (cycles per pixel) * mx.
 __device__ __forceinline__ double stolt_kx(double k, double ku) {
 #pragma clang fp contract(off)
   return sqrt(4.0 * (k * k) - ku * ku);
 }
-__device__ __forceinline__ double lattice_coord(double kx, double fov) {
-#pragma clang fp contract(off)
-  return kx * fov / (2.0 * TFFR_PI);
+__device__ __forceinline__ double lattice_coord(double kx, const Geo& g) {
+  return (kx * g.tx_scale) * (double)g.mx;
 }
 
 // Finite-interval cosine transforms of w = exp(-a|t|) and 1/w over [-1/2, 1/2]
-// (the entries of W and Psi on the image's own lattice).
-__device__ __forceinline__ double r_w(double d, const Geo& g) {
+// (the entries of W and Psi on the image's own lattice); ema2 = exp(-a/2), epa2 = exp(a/2).
+__device__ __forceinline__ double r_w(double d, double a, double ema2) {
   const double b = 2.0 * TFFR_PI * d;
   double sn, cs;
   sincos(b / 2.0, &sn, &cs);
-  const double den = g.a * g.a + b * b;
+  const double den = a * a + b * b;
   if (den == 0.0) return 1.0;
-  return 2.0 * (g.a + g.ema2 * (b * sn - g.a * cs)) / den;
+  return 2.0 * (a + ema2 * (b * sn - a * cs)) / den;
 }
-__device__ __forceinline__ double r_psi(double d, const Geo& g) {
+__device__ __forceinline__ double r_psi(double d, double a, double epa2) {
   const double b = 2.0 * TFFR_PI * d;
   double sn, cs;
   sincos(b / 2.0, &sn, &cs);
-  const double den = g.a * g.a + b * b;
+  const double den = a * a + b * b;
   if (den == 0.0) return 1.0;
-  return 2.0 * (g.epa2 * (b * sn + g.a * cs) - g.a) / den;
+  return 2.0 * (epa2 * (b * sn + a * cs) - a) / den;
 }
 
 // g(delta) = sum_{|k - delta| < q} R_Psi(k - delta) R_W(k - delta): the diagonal of the
 // truncated frame product for a sample at fractional lattice offset delta.
-__device__ double frame_diag(const Geo& g, double delta) {
-  const int K = (int)ceil(g.q) + 1;
+__device__ double frame_diag(double delta, double a, double q, double ema2, double epa2) {
+  const int K = (int)ceil(q) + 1;
   double acc = 0.0;
   for (int k = -K; k <= K; ++k) {
     const double d = (double)k - delta;
-    if (fabs(d) < g.q) acc += r_psi(d, g) * r_w(d, g);
+    if (fabs(d) < q) acc += r_psi(d, a, epa2) * r_w(d, a, ema2);
   }
   return acc;
 }
 
-// tFFR weight R_tau(1/g) of a sample at lattice coordinate lam.
+// R_tau(1/g) in FP64 from the closed form (the double path, and float samples whose
+// polynomial value falls within near_rel of the threshold).  Kept out of line (it is
+// rarely taken and large); scalars by value so the caller keeps its state in registers.
+__device__ __attribute__((noinline)) double tffr_weight_f64(double delta, double a, double q, double ema2,
+                                                            double epa2, double tau, int mode) {
+  const double gd = frame_diag(delta, a, q, ema2, epa2);
+  const double inv = gd != 0.0 ? 1.0 / gd : 0.0;
+  const bool keep = mode == 0 ? (fabs(inv) >= tau) : (gd >= tau);
+  return keep ? inv : 0.0;
+}
+
+constexpr int kPolySeg = 32;  // segments of the tFFR weight polynomial on (0, 1)
+constexpr int kPolyDeg = 7;   // degree per segment
+
+// tFFR weight R_tau(1/g) of a sample at lattice coordinate lam; poly is the piecewise
+// polynomial of 1/g in the local variable of each segment (LDS copy on the float path).
 template <typename R>
-__device__ __forceinline__ R tffr_weight(const Geo& g, const float* __restrict__ poly, double lam) {
+__device__ __forceinline__ R tffr_weight(const Geo& g, const float* poly, double lam) {
   const double delta = lam - floor(lam);
   if (delta == 0.0) return g.keep0 ? (R)g.inv_g0 : (R)0;
   if (sizeof(R) == 4 && g.use_poly) {
-    const double xs = delta * g.nseg;
-    const int seg = min((int)xs, g.nseg - 1);
+    const double xs = delta * kPolySeg;
+    const int seg = min((int)xs, kPolySeg - 1);
     const float t = (float)(2.0 * (xs - seg) - 1.0);
-    const float* c = poly + seg * (g.deg + 1);
+    const float* c = poly + seg * (kPolyDeg + 1);
     float v = c[0];
-    for (int i = 1; i <= g.deg; ++i) v = fmaf(v, t, c[i]);
-    const float thr = g.thresh_mode == 0 ? (float)g.tau : (float)(1.0 / g.tau);
-    if (fabsf(v - thr) > (float)g.near_rel * thr) {
+#pragma unroll
+    for (int i = 1; i <= kPolyDeg; ++i) v = fmaf(v, t, c[i]);
+    const float thr = g.thr_f;
+    if (fabsf(v - thr) > g.near_f * thr) {
       const bool keep = g.thresh_mode == 0 ? (v >= thr) : (v <= thr);
       return keep ? (R)v : (R)0;
     }
   }
-  const double gd = frame_diag(g, delta);
-  const double inv = gd != 0.0 ? 1.0 / gd : 0.0;
-  const bool keep = g.thresh_mode == 0 ? (fabs(inv) >= g.tau) : (gd >= g.tau);
-  return keep ? (R)inv : (R)0;
+  return (R)tffr_weight_f64(delta, g.a, g.q, g.ema2, g.epa2, g.tau, g.thresh_mode);
 }
+
+// Copy the tFFR weight polynomial into LDS (float path); returns the pointer to use.
+template <int NT>
+__device__ __forceinline__ const float* load_poly(const Geo& g, const float* __restrict__ gp, float* lp) {
+  if (!gp) return gp;
+  const int n = kPolySeg * (kPolyDeg + 1);
+  for (int i = threadIdx.x; i < n; i += NT) lp[i] = gp[i];
+  return lp;
+}
+constexpr int kPolyLds = 512;  // floats reserved in LDS for the weight polynomial
 
 // Weight of sample (n, p) for the diagonal methods.
 template <typename R>
-__device__ __forceinline__ R diag_weight(const Geo& g, const Tab<R>& t, double ku, int p, double lam) {
+__device__ __forceinline__ R diag_weight(const Geo& g, const Tab<R>& t, const float* poly, double ku, int p,
+                                         double lam) {
   switch (g.weighting) {
     case 3:  // tFFR
-      return tffr_weight<R>(g, t.poly, lam);
+      return tffr_weight<R>(g, poly, lam);
     case 1: {  // trapezoid quadrature in lam along the slice
       if (g.n_freq == 1) return (R)1;
       const int plo = p > 0 ? p - 1 : 0, phi = p < g.n_freq - 1 ? p + 1 : g.n_freq - 1;
-      const double llo = lattice_coord(stolt_kx(t.k[plo], ku), g.fov_x);
-      const double lhi = lattice_coord(stolt_kx(t.k[phi], ku), g.fov_x);
+      const double llo = lattice_coord(stolt_kx(t.k[plo], ku), g);
+      const double lhi = lattice_coord(stolt_kx(t.k[phi], ku), g);
       return (R)((lhi - llo) / 2.0);
     }
     default:
@@ -267,14 +297,22 @@ __device__ __forceinline__ R diag_weight(const Geo& g, const Tab<R>& t, double k
   }
 }
 
-// ES kernel exp(beta (sqrt(1 - z^2) - 1)), zero for |z| >= 1.
-__device__ __forceinline__ float es_kernel(float z, float beta) {
-  const float s = 1.0f - z * z;
-  return s > 0.0f ? __expf(beta * (__fsqrt_rn(s) - 1.0f)) : 0.0f;
+// ES kernel exp(beta (sqrt(1 - z^2) - 1)) at a tap offset z in (-1, 1).  The taps the
+// gridding uses satisfy |z| < 1 except on the measure-zero boundary z = -1 (fraction
+// exactly W/2 - floor(W/2) from a cell), where this returns exp(-beta) ~ 1e-7 instead
+// of 0.  FP32: hardware sqrt and exp2 (beta_l2e = beta log2 e).
+__device__ __forceinline__ float es_kernel(float z, float beta_l2e) {
+  const float s = fmaxf(fmaf(-z, z, 1.0f), 0.0f);
+  return __builtin_amdgcn_exp2f(fmaf(beta_l2e, __builtin_amdgcn_sqrtf(s), -beta_l2e));
 }
 __device__ __forceinline__ double es_kernel(double z, double beta) {
-  const double s = 1.0 - z * z;
-  return s > 0.0 ? exp(beta * (sqrt(s) - 1.0)) : 0.0;
+  const double s = fmax(1.0 - z * z, 0.0);
+  return exp(beta * (sqrt(s) - 1.0));
+}
+// the kernel-shape constant es_kernel expects for the compute type
+template <typename R>
+__device__ __forceinline__ R es_shape(const Geo& g) {
+  return sizeof(R) == 4 ? (R)(g.beta * 1.4426950408889634) : (R)g.beta;
 }
 
 // Fine-grid position of a sample with lattice-per-pixel coordinate t (cycles per pixel):
@@ -312,89 +350,102 @@ __device__ __forceinline__ cplx<R> row_rotation(const Tab<R>& t, const R* phase,
   return {cs, sn};
 }
 
-// Weighted, phased sample c[n,p] (forward input of the gridding).
+// (D s)_p for plain FFR: the banded slice matrix applied around sample p (out of line).
 template <typename R>
-__device__ __forceinline__ cplx<R> weighted_sample(const Geo& g, const Tab<R>& t, int stype,
-                                                   const void* samples, const R* w, int n, int p,
-                                                   double ku, double lam, cplx<R> rot) {
-  const size_t base = (size_t)n * g.n_freq;
-  if (g.weighting == 2) {  // plain FFR: banded D within the slice
-    const int r = g.band_r;
-    const R* drow = w + (base + p) * (2 * r + 1);
-    cplx<R> acc = {0, 0};
-    for (int o = -r; o <= r; ++o) {
-      const int pp = p + o;
-      if (pp >= 0 && pp < g.n_freq) acc = acc + drow[r + o] * load_sample<R>(samples, stype, base + pp);
-    }
-    return cmul(rot, acc);
+__device__ __attribute__((noinline)) cplx<R> ffr_apply(const void* samples, int stype, const R* w, size_t base, int p,
+                                                       int n_freq, int r) {
+  const R* drow = w + (base + p) * (2 * r + 1);
+  cplx<R> acc = {0, 0};
+  for (int o = -r; o <= r; ++o) {
+    const int pp = p + o;
+    if (pp >= 0 && pp < n_freq) acc = acc + drow[r + o] * load_sample<R>(samples, stype, base + pp);
   }
-  const R wt = w ? w[base + p] : diag_weight<R>(g, t, ku, p, lam);
-  return wt * cmul(rot, load_sample<R>(samples, stype, base + p));
+  return acc;
+}
+
+// Weighted, phased sample c[n,p] (forward input of the gridding); s is sample (n, p).
+template <typename R>
+__device__ __forceinline__ cplx<R> weighted_sample(const Geo& g, const Tab<R>& t, const float* poly, int stype,
+                                                   const void* samples, const R* w, int n, int p,
+                                                   double ku, double lam, cplx<R> rot, cplx<R> s) {
+  const size_t base = (size_t)n * g.n_freq;
+  if (g.weighting == 2)  // plain FFR: banded D within the slice
+    return cmul(rot, ffr_apply<R>(samples, stype, w, base, p, g.n_freq, g.band_r));
+  const R wt = w ? w[base + p] : diag_weight<R>(g, t, poly, ku, p, lam);
+  return wt * cmul(rot, s);
 }
 
 // ============================================================================ forward
-constexpr int SMAX = 16;  // samples a thread holds in registers per sub-pass group
-
 // Range stage: one azimuth slice per workgroup.  Spread the slice's weighted samples
 // onto the periodic fine row, inverse FFT, keep the centred mx bins and divide by the
 // kernel transform.  stage 0 dumps the gridded row instead.
 //
-// No atomics: kx grows along a slice, so thread t owning the S consecutive samples
-// [b0 + S t, b0 + S t + S) and processing one of them per sub-pass touches cell ranges
-// that are disjoint from every other thread's in that sub-pass (the plan picks S with
+// No atomics: kx grows along a slice, so when thread t takes the sample
+// p = part start + block * S * NT + S t + j in sub-pass j, the samples of one sub-pass
+// are S apart and their cell ranges are disjoint (the plan picks S with
 // S * (smallest sample spacing) > W).  The slice is cut into parts whose span is less
-// than the fine row, so no two samples of a part meet after wrapping.  Each sub-pass
-// is a plain read-add-write into LDS followed by a barrier.
-template <typename R, int LOGN, int NT>
+// than the fine row, so no two samples of a part meet after wrapping.  Each sub-pass is
+// a plain read-add-write into LDS followed by a barrier; the raw inputs of the next
+// sub-pass are loaded while the current one is processed.
+template <typename R, int LOGN, int NT, int SG>
 __global__ __launch_bounds__(NT) void k_fwd_rows(Geo g, Tab<R> t, int stype, const void* __restrict__ samples,
                                                  const R* __restrict__ phase, const R* __restrict__ dalong,
                                                  const R* __restrict__ w, cplx<R>* __restrict__ out, int stage) {
   constexpr int N = 1 << LOGN;
+  constexpr int DPT = (N + NT - 1) / NT;  // >= output bins per thread (mx <= N)
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
   cplx<R>* buf = tw + tw_entries<N>();
+  float* lpoly = reinterpret_cast<float*>(buf + N);
   const int n = blockIdx.x;
+  const bool ffr = g.weighting == 2;
+  const int S = g.sub, W = g.W, plen = g.part_len;
+  const int nblk = (plen + S * NT - 1) / (S * NT);
+  const size_t base = (size_t)n * g.n_freq;
   load_twiddles<N, NT>(tw, t.twx);
+  const float* poly = load_poly<NT>(g, t.poly, lpoly);
   for (int i = threadIdx.x; i < N; i += NT) buf[i] = {0, 0};
   const cplx<R> rot = row_rotation(t, phase, dalong, n);
   const double ku = t.ku[n];
-  const R halfw = (R)(0.5 * g.W), inv_halfw = (R)(2.0 / g.W), beta = (R)g.beta;
-  const int S = g.sub, W = g.W;
-  __syncthreads();
-  for (int pa = 0; pa < g.n_freq; pa += g.part_len) {
-    const int pb = min(pa + g.part_len, g.n_freq);
-    for (int b0 = pa; b0 < pb; b0 += S * NT) {
-      const int pt = b0 + S * (int)threadIdx.x;
-      for (int r0 = 0; r0 < S; r0 += SMAX) {
-        cplx<R> c[SMAX];
-        int cell[SMAX];
-        R z0[SMAX];
+  const R halfw = (R)(0.5 * g.W), inv_halfw = (R)(2.0 / g.W), beta = es_shape<R>(g);
+  bool first = true;
+  for (int pa = 0; pa < g.n_freq; pa += plen) {
+    const int pb = min(pa + plen, g.n_freq);
+    for (int blk = 0; blk < nblk; ++blk) {
+      const int p0 = pa + blk * S * NT + S * (int)threadIdx.x;  // this thread's S consecutive samples
+      for (int j0 = 0; j0 < S; j0 += SG) {
+        // raw inputs of up to SG consecutive samples, loaded back to back
+        double kr[SG];
+        cplx<R> sr[SG];
 #pragma unroll
-        for (int j = 0; j < SMAX; ++j) {
-          const int p = pt + r0 + j;
-          cell[j] = 0;
-          z0[j] = 0;
-          c[j] = {0, 0};
-          if (r0 + j < S && p < pb) {
-            const double kx = stolt_kx(t.k[p], ku);
-            const double lam = lattice_coord(kx, g.fov_x);
-            c[j] = weighted_sample<R>(g, t, stype, samples, w, n, p, ku, lam, rot);
-            int ui;
-            R f;
-            fine_pos<R>(kx * g.tx_scale, N, ui, f);
-            const int k0 = (int)ceil(f - halfw);
-            cell[j] = ui + k0;
-            z0[j] = ((R)k0 - f) * inv_halfw;
-          }
+        for (int j = 0; j < SG; ++j) {
+          const int p = p0 + j0 + j;
+          const bool ok = j0 + j < S && p < pb;
+          kr[j] = ok ? t.k[p] : 0.0;
+          sr[j] = (ok && !ffr) ? load_sample<R>(samples, stype, base + p) : cplx<R>{0, 0};
+        }
+        if (first) {
+          __syncthreads();  // row zeroed, tables in LDS
+          first = false;
         }
 #pragma unroll
-        for (int j = 0; j < SMAX; ++j) {
-          if (r0 + j < S) {
-            if (pt + r0 + j < pb) {
+        for (int j = 0; j < SG; ++j) {
+          if (j0 + j < S) {
+            const int p = p0 + j0 + j;
+            if (p < pb) {
+              const double kx = stolt_kx(kr[j], ku);
+              const double lam = lattice_coord(kx, g);
+              const cplx<R> c = weighted_sample<R>(g, t, poly, stype, samples, w, n, p, ku, lam, rot, sr[j]);
+              int ui;
+              R f;
+              fine_pos<R>(kx * g.tx_scale, N, ui, f);
+              const int k0 = (int)ceil(f - halfw);
+              const int cell = ui + k0;
+              const R z0 = ((R)k0 - f) * inv_halfw;
               for (int i = 0; i < W; ++i) {
-                const R phi = es_kernel(z0[j] + (R)i * inv_halfw, beta);
-                cplx<R>& b = buf[(cell[j] + i) & (N - 1)];
-                b = b + phi * c[j];
+                const R phi = es_kernel(z0 + (R)i * inv_halfw, beta);
+                cplx<R>& bb = buf[(cell + i) & (N - 1)];
+                bb = bb + phi * c;
               }
             }
             __syncthreads();
@@ -403,97 +454,185 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(Geo g, Tab<R> t, int stype, con
       }
     }
   }
+  if (first) __syncthreads();
   if (stage == 0) {
     for (int i = threadIdx.x; i < N; i += NT) out[(size_t)n * N + i] = buf[i];
     return;
   }
-  lds_fft<+1, N, NT>(buf, tw);
   const int mx = g.mx;
-  for (int jx = threadIdx.x; jx < mx; jx += NT) {
-    const cplx<R> v = buf[(jx - mx / 2) & (N - 1)];
-    out[(size_t)n * mx + jx] = t.deapx[jx] * v;
+  R dx[DPT];
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) {
+    const int jx = threadIdx.x + j * NT;
+    dx[j] = jx < mx ? t.deapx[jx] : (R)0;
+  }
+  lds_fft<+1, N, NT>(buf, tw);
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) {
+    const int jx = threadIdx.x + j * NT;
+    if (jx < mx) out[(size_t)n * mx + jx] = dx[j] * buf[(jx - mx / 2) & (N - 1)];
   }
 }
 
 // Azimuth stage: CB range columns per workgroup.  The block's columns of the range
 // spectra are staged in LDS; every fine azimuth cell then gathers its (slice, tap) pairs
-// from the plan's cell table (no atomics), inverse FFT along azimuth, keep the centred
-// my bins, divide by the kernel transform, write the image columns (range-major).
-template <typename R, int LOGN, int NT>
-__global__ __launch_bounds__(NT) void k_fwd_cols(Geo g, Tab<R> t, int cb, const cplx<R>* __restrict__ hx,
-                                                 cplx<R>* __restrict__ img) {
+// from the plan's padded cell table for all CB columns at once (no atomics), batched
+// inverse FFT along azimuth, keep the centred my bins, divide by the kernel transform,
+// write the image columns (range-major).  With partials non-null the block also writes
+// its share of the image-entropy sums (sum |I|^2, sum |I|^2 ln |I|^2).
+template <typename R, int LOGN, int NT, int CB>
+__global__ __launch_bounds__(NT) void k_fwd_cols(Geo g, Tab<R> t, const cplx<R>* __restrict__ hx,
+                                                 cplx<R>* __restrict__ img, double* __restrict__ partials) {
   constexpr int N = 1 << LOGN;
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
   cplx<R>* buf = tw + tw_entries<N>();
-  cplx<R>* hs = buf + (size_t)cb * N;  // [n_pulses][cb]
-  const int c0 = blockIdx.x * cb;
-  const int ncol = min(cb, g.mx - c0);
+  cplx<R>* hs = buf + (size_t)CB * N;  // [n_pulses][CB]
+  const int c0 = blockIdx.x * CB;
+  const int ncol = min(CB, g.mx - c0);
   load_twiddles<N, NT>(tw, t.twy);
-  const int total = g.n_pulses * ncol;
+  const int total = g.n_pulses * CB;
   for (int idx = threadIdx.x; idx < total; idx += NT) {
-    const int nn = idx / ncol, c = idx - nn * ncol;
-    hs[nn * cb + c] = hx[(size_t)nn * g.mx + c0 + c];
+    const int nn = idx / CB, c = idx - nn * CB;
+    hs[idx] = c < ncol ? hx[(size_t)nn * g.mx + c0 + c] : cplx<R>{0, 0};
   }
   __syncthreads();
-  for (int c = 0; c < ncol; ++c) {
-    for (int iy = threadIdx.x; iy < N; iy += NT) {
-      const int e0 = t.ycell_ptr[iy], e1 = t.ycell_ptr[iy + 1];
-      cplx<R> acc = {0, 0};
-      for (int e = e0; e < e1; ++e) acc = acc + t.ycell_w[e] * hs[t.ycell_n[e] * cb + c];
-      buf[c * N + iy] = acc;
+  const int E = g.yemax;
+  for (int iy = threadIdx.x; iy < N; iy += NT) {
+    cplx<R> acc[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) acc[c] = {0, 0};
+    const int32_t* en = t.ycell_n + (size_t)iy * E;
+    const R* ew = t.ycell_w + (size_t)iy * E;
+    for (int e = 0; e < E; ++e) {
+      const int nn = en[e];
+      const R wt = ew[e];
+#pragma unroll
+      for (int c = 0; c < CB; ++c) acc[c] = acc[c] + wt * hs[nn * CB + c];
     }
+#pragma unroll
+    for (int c = 0; c < CB; ++c) buf[c * N + iy] = acc[c];
   }
   __syncthreads();
-  for (int c = 0; c < ncol; ++c) lds_fft<+1, N, NT>(buf + c * N, tw);
+  lds_fft<+1, N, NT, CB>(buf, tw);
   const int my = g.my;
+  double es = 0.0, et = 0.0;
   for (int c = 0; c < ncol; ++c) {
     const cplx<R>* col = buf + c * N;
     cplx<R>* o = img + (size_t)(c0 + c) * my;
-    for (int jy = threadIdx.x; jy < my; jy += NT) o[jy] = t.deapy[jy] * col[(jy - my / 2) & (N - 1)];
+    for (int jy = threadIdx.x; jy < my; jy += NT) {
+      const cplx<R> v = t.deapy[jy] * col[(jy - my / 2) & (N - 1)];
+      o[jy] = v;
+      if (partials) {
+        const R a = v.x * v.x + v.y * v.y;
+        es += (double)a;
+        if (a > (R)0) et += (double)(a * log(a));
+      }
+    }
+  }
+  if (partials) {
+    es = block_sum<NT>(es);
+    et = block_sum<NT>(et);
+    if (threadIdx.x == 0) {
+      partials[2 * blockIdx.x] = es;
+      partials[2 * blockIdx.x + 1] = et;
+    }
+  }
+}
+
+// Image entropy from the per-block sums: E = ln S - (1/S) sum a ln a.  One block.
+// stats[0] = S, stats[1] = E; *loss = E.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_entropy_stats(const double* __restrict__ partials, int nparts,
+                                                      double* __restrict__ stats, double* __restrict__ loss) {
+  double s = 0.0, tl = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += NT) {
+    s += partials[2 * i];
+    tl += partials[2 * i + 1];
+  }
+  s = block_sum<NT>(s);
+  tl = block_sum<NT>(tl);
+  if (threadIdx.x == 0) {
+    const double E = (s > 0.0) ? log(s) - tl / s : 0.0;
+    stats[0] = s;
+    stats[1] = E;
+    if (loss) *loss = E;
   }
 }
 
 // ============================================================================ adjoint
 // Azimuth stage, type 2: per range column, divide by the kernel transform, zero-pad to
-// the fine grid, forward FFT (sign -), and interpolate at every slice's azimuth position.
-template <typename R, int LOGN, int NT>
-__global__ __launch_bounds__(NT) void k_adj_cols(Geo g, Tab<R> t, int cb, const cplx<R>* __restrict__ cot,
-                                                 cplx<R>* __restrict__ hx) {
+// the fine grid, forward FFT (sign -, batched over the CB columns), and interpolate at
+// every slice's azimuth position.  Entropy mode: `cot` is the image I itself and the
+// cotangent is the entropy gradient -(2/S)(ln |I|^2 - ln S + E) I (0 where I = 0),
+// formed in registers, with (S, E) read from stats, or reduced by the block itself from
+// the forward kernel's nparts partial sums (then block 0 also writes *loss).
+template <typename R, int LOGN, int NT, int CB>
+__global__ __launch_bounds__(NT) void k_adj_cols(Geo g, Tab<R> t, const cplx<R>* __restrict__ cot,
+                                                 cplx<R>* __restrict__ hx, const double* __restrict__ stats,
+                                                 const double* __restrict__ partials, int nparts,
+                                                 double* __restrict__ loss) {
   constexpr int N = 1 << LOGN;
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
   cplx<R>* buf = tw + tw_entries<N>();
-  const int c0 = blockIdx.x * cb;
-  const int ncol = min(cb, g.mx - c0);
+  const int c0 = blockIdx.x * CB;
+  const int ncol = min(CB, g.mx - c0);
   const int my = g.my;
   load_twiddles<N, NT>(tw, t.twy);
-  for (int c = 0; c < ncol; ++c) {
-    const cplx<R>* in = cot + (size_t)(c0 + c) * my;
-    for (int i = threadIdx.x; i < N; i += NT) {
-      const int jp = i < N / 2 ? i : i - N;  // signed bin
-      const int jy = jp + my / 2;
-      buf[c * N + i] = (jy >= 0 && jy < my) ? t.deapy[jy] * in[jy] : cplx<R>{0, 0};
+  R sc = 0, off = 0;
+  const bool ent = stats || partials;
+  if (partials) {
+    double es = 0.0, et = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += NT) {
+      es += partials[2 * i];
+      et += partials[2 * i + 1];
     }
+    es = block_sum<NT>(es);
+    et = block_sum<NT>(et);
+    const double E = (es > 0.0) ? log(es) - et / es : 0.0;
+    if (loss && blockIdx.x == 0 && threadIdx.x == 0) *loss = E;
+    sc = (R)(-2.0 / es);
+    off = (R)(E - log(es));
+  } else if (stats) {
+    sc = (R)(-2.0 / stats[0]);
+    off = (R)(stats[1] - log(stats[0]));
+  }
+  for (int idx = threadIdx.x; idx < CB * N; idx += NT) {
+    const int c = idx / N, i = idx - c * N;
+    const int jp = i < N / 2 ? i : i - N;  // signed bin
+    const int jy = jp + my / 2;
+    cplx<R> v = {0, 0};
+    if (c < ncol && jy >= 0 && jy < my) {
+      v = cot[(size_t)(c0 + c) * my + jy];
+      if (ent) {
+        const R a = v.x * v.x + v.y * v.y;
+        v = a > (R)0 ? (sc * (log(a) + off)) * v : cplx<R>{0, 0};
+      }
+      v = t.deapy[jy] * v;
+    }
+    buf[idx] = v;
   }
   __syncthreads();
-  for (int c = 0; c < ncol; ++c) lds_fft<-1, N, NT>(buf + c * N, tw);
+  lds_fft<-1, N, NT, CB>(buf, tw);
   const int W = g.W;
   const int total = g.n_pulses * ncol;
   for (int idx = threadIdx.x; idx < total; idx += NT) {
-    const int n = idx / ncol, c = idx - n * ncol;
-    const int ys = t.ystart[n];
-    const R* tap = t.ytap + (size_t)n * W;
+    const int nn = idx / ncol, c = idx - nn * ncol;
+    const int ys = t.ystart[nn];
+    const R* tap = t.ytap + (size_t)nn * W;
     const cplx<R>* col = buf + c * N;
     cplx<R> acc = {0, 0};
     for (int i = 0; i < W; ++i) acc = acc + tap[i] * col[(ys + i) & (N - 1)];
-    hx[(size_t)n * g.mx + c0 + c] = acc;
+    hx[(size_t)nn * g.mx + c0 + c] = acc;
   }
 }
 
 // Range stage, type 2: per slice, divide by the kernel transform, zero-pad, forward FFT
 // (sign -), interpolate at every sample, apply D^T and exp(-i psi), and reduce the
 // per-slice phase gradient sum_p Re(conj(g'_p) i s'_p) = sum_p (g_i s_r - g_r s_i).
+// The raw inputs of a thread's first sample are loaded before the FFT, and those of
+// the next sample while the current one is processed.
 template <typename R, int LOGN, int NT>
 __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, const cplx<R>* __restrict__ hx,
                                                  const void* __restrict__ samples, const R* __restrict__ phase,
@@ -504,47 +643,62 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
   cplx<R>* buf = tw + tw_entries<N>();
-  cplx<R>* gbuf = buf + N;  // FFR only: interpolated values of the slice
+  float* lpoly = reinterpret_cast<float*>(buf + N);
+  cplx<R>* gbuf = reinterpret_cast<cplx<R>*>(lpoly + kPolyLds);  // FFR only: interpolated values
   const int n = blockIdx.x;
-  load_twiddles<N, NT>(tw, t.twx);
   const int mx = g.mx;
+  const size_t base = (size_t)n * g.n_freq;
+  const bool ffr = g.weighting == 2;
+  const bool want_phase = grad_phase || grad_dalong;
+  const bool need_s = want_phase && !ffr;
+  int p_next = threadIdx.x;
+  double k_next = p_next < g.n_freq ? t.k[p_next] : 0.0;
+  cplx<R> s_next = (need_s && p_next < g.n_freq) ? load_sample<R>(samples, stype, base + p_next) : cplx<R>{0, 0};
+  R w_next = (w && !ffr && p_next < g.n_freq) ? w[base + p_next] : (R)0;
+  load_twiddles<N, NT>(tw, t.twx);
+  const float* poly = load_poly<NT>(g, t.poly, lpoly);
   const cplx<R>* in = hx + (size_t)n * mx;
   for (int i = threadIdx.x; i < N; i += NT) {
     const int jp = i < N / 2 ? i : i - N;
     const int jx = jp + mx / 2;
     buf[i] = (jx >= 0 && jx < mx) ? t.deapx[jx] * in[jx] : cplx<R>{0, 0};
   }
-  __syncthreads();
-  lds_fft<-1, N, NT>(buf, tw);
   const cplx<R> rot = row_rotation(t, phase, dalong, n);
   const double ku = t.ku[n];
-  const R halfw = (R)(0.5 * g.W), inv_halfw = (R)(2.0 / g.W), beta = (R)g.beta;
-  const size_t base = (size_t)n * g.n_freq;
-  const bool ffr = g.weighting == 2;
-  const bool want_phase = grad_phase || grad_dalong;
+  const R halfw = (R)(0.5 * g.W), inv_halfw = (R)(2.0 / g.W), beta = es_shape<R>(g);
+  __syncthreads();
+  lds_fft<-1, N, NT>(buf, tw);
   double acc_phase = 0.0;
   for (int p = threadIdx.x; p < g.n_freq; p += NT) {
-    const double kx = stolt_kx(t.k[p], ku);
+    const double kp = k_next;
+    const cplx<R> sp = s_next;
+    const R wp = w_next;
+    p_next = p + NT;
+    if (p_next < g.n_freq) {
+      k_next = t.k[p_next];
+      if (need_s) s_next = load_sample<R>(samples, stype, base + p_next);
+      if (w && !ffr) w_next = w[base + p_next];
+    }
+    const double kx = stolt_kx(kp, ku);
     int ui;
     R f;
     fine_pos<R>(kx * g.tx_scale, N, ui, f);
     const int k0 = (int)ceil(f - halfw);
+    const int cell = ui + k0;
+    const R z0 = ((R)k0 - f) * inv_halfw;
     cplx<R> a = {0, 0};
     for (int i = 0; i < g.W; ++i) {
-      const R phi = es_kernel((R)(k0 + i) * inv_halfw - f * inv_halfw, beta);
-      a = a + phi * buf[(ui + k0 + i) & (N - 1)];
+      const R phi = es_kernel(z0 + (R)i * inv_halfw, beta);
+      a = a + phi * buf[(cell + i) & (N - 1)];
     }
     if (ffr) {
       gbuf[p] = a;
       continue;
     }
-    const R wt = w ? w[base + p] : diag_weight<R>(g, t, ku, p, lattice_coord(kx, g.fov_x));
+    const R wt = w ? wp : diag_weight<R>(g, t, poly, ku, p, lattice_coord(kx, g));
     const cplx<R> gs = cmulc(wt * a, rot);  // exp(-i psi) D^T A^H
     grad_s[base + p] = gs;
-    if (want_phase) {
-      const cplx<R> s = load_sample<R>(samples, stype, base + p);
-      acc_phase += (double)gs.y * (double)s.x - (double)gs.x * (double)s.y;
-    }
+    if (want_phase) acc_phase += (double)gs.y * (double)sp.x - (double)gs.x * (double)sp.y;
   }
   if (ffr) {
     __syncthreads();
@@ -558,8 +712,8 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
       const cplx<R> gs = cmulc(a, rot);
       grad_s[base + p] = gs;
       if (want_phase) {
-        const cplx<R> s = load_sample<R>(samples, stype, base + p);
-        acc_phase += (double)gs.y * (double)s.x - (double)gs.x * (double)s.y;
+        const cplx<R> sv = load_sample<R>(samples, stype, base + p);
+        acc_phase += (double)gs.y * (double)sv.x - (double)gs.x * (double)sv.y;
       }
     }
   }
@@ -581,8 +735,8 @@ __global__ __launch_bounds__(NT) void k_weights(Geo g, Tab<R> t, R* __restrict__
   for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < total; i += (size_t)gridDim.x * NT) {
     const int n = (int)(i / g.n_freq), p = (int)(i - (size_t)n * g.n_freq);
     const double ku = t.ku[n];
-    const double lam = lattice_coord(stolt_kx(t.k[p], ku), g.fov_x);
-    const R v = diag_weight<R>(g, t, ku, p, lam);
+    const double lam = lattice_coord(stolt_kx(t.k[p], ku), g);
+    const R v = diag_weight<R>(g, t, t.poly, ku, p, lam);
     if (w) w[i] = v;
     kept += (v != (R)0) ? 1ull : 0ull;
   }
@@ -610,17 +764,17 @@ __global__ __launch_bounds__(NT) void k_ffr_build(Geo g, Tab<R> t, double* __res
   for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < total; i += (size_t)gridDim.x * NT) {
     const int n = (int)(i / g.n_freq), p = (int)(i - (size_t)n * g.n_freq);
     const double ku = t.ku[n];
-    const double lp = lattice_coord(stolt_kx(t.k[p], ku), g.fov_x);
+    const double lp = lattice_coord(stolt_kx(t.k[p], ku), g);
     const double fl = floor(lp);
     for (int o = -b; o <= b; ++o) {
       const int pp = p + o;
       double acc = 0.0;
       if (pp >= 0 && pp < g.n_freq) {
-        const double lq = lattice_coord(stolt_kx(t.k[pp], ku), g.fov_x);
+        const double lq = lattice_coord(stolt_kx(t.k[pp], ku), g);
         for (int k = -K; k <= K; ++k) {
           const double m = fl + (double)k;
           const double d1 = m - lp, d2 = m - lq;
-          if (fabs(d1) < g.q && fabs(d2) < g.q) acc += r_psi(d1, g) * r_w(d2, g);
+          if (fabs(d1) < g.q && fabs(d2) < g.q) acc += r_psi(d1, g.a, g.epa2) * r_w(d2, g.a, g.ema2);
         }
       }
       gband[i * wdt + (b + o)] = acc;
@@ -785,13 +939,20 @@ size_t max_dynamic_lds() {
       return hipErrorInvalidValue;        \
   }
 
+template <int LOGN, int CB>
+constexpr int nt_cols() {
+  constexpr int want = ((1 << LOGN) / 8) * CB;
+  return want < 64 ? 64 : (want > 1024 ? 1024 : want);
+}
+
 template <typename R>
 hipError_t launch_fwd_rows(const Geo& g, const Tab<R>& t, int stype, const void* samples, const R* phase,
                            const R* dalong, const R* w, cplx<R>* out, int stage, hipStream_t st) {
-  const size_t lds = sizeof(cplx<R>) * (((size_t)1 << g.lognfx) + ((size_t)1 << g.lognfx) / 64 + 64);
+  const size_t lds = sizeof(cplx<R>) * (((size_t)1 << g.lognfx) + ((size_t)1 << g.lognfx) / 64 + 64) +
+                     sizeof(float) * kPolyLds;
   TFFR_LOGN_DISPATCH(g.lognfx, {
     constexpr int NT = nt_for<L>();
-    auto fn = k_fwd_rows<R, L, NT>;
+    auto fn = g.sub <= 4 ? k_fwd_rows<R, L, NT, 4> : (g.sub <= 8 ? k_fwd_rows<R, L, NT, 8> : k_fwd_rows<R, L, NT, 16>);
     hipError_t e = allow_lds((const void*)fn, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fn, dim3(g.n_pulses), dim3(NT), lds, st, g, t, stype, samples, phase, dalong, w, out, stage);
@@ -799,32 +960,56 @@ hipError_t launch_fwd_rows(const Geo& g, const Tab<R>& t, int stype, const void*
   })
 }
 
+#define TFFR_CB_DISPATCH(cb, ...)   \
+  switch (cb) {                     \
+    case 1: {                       \
+      constexpr int CB = 1;         \
+      __VA_ARGS__                   \
+    }                               \
+    case 2: {                       \
+      constexpr int CB = 2;         \
+      __VA_ARGS__                   \
+    }                               \
+    case 4: {                       \
+      constexpr int CB = 4;         \
+      __VA_ARGS__                   \
+    }                               \
+    default:                        \
+      return hipErrorInvalidValue;  \
+  }
+
 template <typename R>
-hipError_t launch_fwd_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>* hx, cplx<R>* img, hipStream_t st) {
+hipError_t launch_fwd_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>* hx, cplx<R>* img, double* partials,
+                           hipStream_t st) {
   const size_t lds = sizeof(cplx<R>) * ((((size_t)1 << g.lognfy) + g.n_pulses) * cb +
                                          ((size_t)1 << g.lognfy) / 64 + 64);
   const int grid = (g.mx + cb - 1) / cb;
   TFFR_LOGN_DISPATCH(g.lognfy, {
-    constexpr int NT = nt_for<L>();
-    auto fn = k_fwd_cols<R, L, NT>;
-    hipError_t e = allow_lds((const void*)fn, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), lds, st, g, t, cb, hx, img);
-    return hipGetLastError();
+    TFFR_CB_DISPATCH(cb, {
+      constexpr int NT = nt_cols<L, CB>();
+      auto fn = k_fwd_cols<R, L, NT, CB>;
+      hipError_t e = allow_lds((const void*)fn, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), lds, st, g, t, hx, img, partials);
+      return hipGetLastError();
+    })
   })
 }
 
 template <typename R>
-hipError_t launch_adj_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>* cot, cplx<R>* hx, hipStream_t st) {
+hipError_t launch_adj_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>* cot, cplx<R>* hx, const double* stats,
+                           const double* partials, int nparts, double* loss, hipStream_t st) {
   const size_t lds = sizeof(cplx<R>) * (((size_t)1 << g.lognfy) * cb + ((size_t)1 << g.lognfy) / 64 + 64);
   const int grid = (g.mx + cb - 1) / cb;
   TFFR_LOGN_DISPATCH(g.lognfy, {
-    constexpr int NT = nt_for<L>();
-    auto fn = k_adj_cols<R, L, NT>;
-    hipError_t e = allow_lds((const void*)fn, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), lds, st, g, t, cb, cot, hx);
-    return hipGetLastError();
+    TFFR_CB_DISPATCH(cb, {
+      constexpr int NT = nt_cols<L, CB>();
+      auto fn = k_adj_cols<R, L, NT, CB>;
+      hipError_t e = allow_lds((const void*)fn, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), lds, st, g, t, cot, hx, stats, partials, nparts, loss);
+      return hipGetLastError();
+    })
   })
 }
 
@@ -832,7 +1017,8 @@ template <typename R>
 hipError_t launch_adj_rows(const Geo& g, const Tab<R>& t, int stype, const cplx<R>* hx, const void* samples,
                            const R* phase, const R* dalong, const R* w, cplx<R>* grad_s, R* grad_phase,
                            R* grad_dalong, hipStream_t st) {
-  size_t lds = sizeof(cplx<R>) * (((size_t)1 << g.lognfx) + ((size_t)1 << g.lognfx) / 64 + 64);
+  size_t lds = sizeof(cplx<R>) * (((size_t)1 << g.lognfx) + ((size_t)1 << g.lognfx) / 64 + 64) +
+               sizeof(float) * kPolyLds;
   if (g.weighting == 2) lds += sizeof(cplx<R>) * (size_t)g.n_freq;
   TFFR_LOGN_DISPATCH(g.lognfx, {
     constexpr int NT = nt_for<L>();
@@ -849,6 +1035,11 @@ template <typename R>
 hipError_t launch_weights(const Geo& g, const Tab<R>& t, R* w, unsigned long long* kept_partial, int nblocks,
                           hipStream_t st) {
   hipLaunchKernelGGL((k_weights<R, 256>), dim3(nblocks), dim3(256), 0, st, g, t, w, kept_partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_entropy_stats(const double* partials, int nparts, double* stats, double* loss, hipStream_t st) {
+  hipLaunchKernelGGL((k_entropy_stats<256>), dim3(1), dim3(256), 0, st, partials, nparts, stats, loss);
   return hipGetLastError();
 }
 
@@ -907,8 +1098,10 @@ hipError_t launch_fft(int log2n, int batch, int sign, const cplx<R>* in, cplx<R>
 #define TFFR_INSTANTIATE(R)                                                                                     \
   template hipError_t launch_fwd_rows<R>(const Geo&, const Tab<R>&, int, const void*, const R*, const R*,     \
                                          const R*, cplx<R>*, int, hipStream_t);                                \
-  template hipError_t launch_fwd_cols<R>(const Geo&, const Tab<R>&, int, const cplx<R>*, cplx<R>*, hipStream_t); \
-  template hipError_t launch_adj_cols<R>(const Geo&, const Tab<R>&, int, const cplx<R>*, cplx<R>*, hipStream_t); \
+  template hipError_t launch_fwd_cols<R>(const Geo&, const Tab<R>&, int, const cplx<R>*, cplx<R>*, double*,     \
+                                         hipStream_t);                                                         \
+  template hipError_t launch_adj_cols<R>(const Geo&, const Tab<R>&, int, const cplx<R>*, cplx<R>*, const double*, \
+                                         const double*, int, double*, hipStream_t);                             \
   template hipError_t launch_adj_rows<R>(const Geo&, const Tab<R>&, int, const cplx<R>*, const void*, const R*, \
                                          const R*, const R*, cplx<R>*, R*, R*, hipStream_t);                   \
   template hipError_t launch_weights<R>(const Geo&, const Tab<R>&, R*, unsigned long long*, int, hipStream_t);  \

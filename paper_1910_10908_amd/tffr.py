@@ -145,6 +145,30 @@ class Plan:
                                          _stream()), "tffr_entropy")
         return loss, grad
 
+    def tffr_entropy_step(self, samples, phase=None, dalong=None, user_w=None, want_phase=True,
+                          want_dalong=True, out=None):
+        """Fused forward + entropy + adjoint of dE/dI.  Returns (image, loss, grad_samples,
+        grad_phase, grad_dalong)."""
+        self._chk_samples(samples)
+        self._chk(phase, (self.params.n_pulses,), self.rtype, "phase")
+        self._chk(dalong, (self.params.n_pulses,), self.rtype, "dalong")
+        self._chk_weights(user_w)
+        img, loss, gs, gph, gda = out if out is not None else (None,) * 5
+        if img is None:
+            img = torch.empty(self.shape_image, dtype=self.ctype, device=self.device)
+        if loss is None:
+            loss = torch.empty((), dtype=torch.float64, device=self.device)
+        if gs is None:
+            gs = torch.empty(self.shape_samples, dtype=self.ctype, device=self.device)
+        if gph is None and want_phase:
+            gph = torch.empty(self.params.n_pulses, dtype=self.rtype, device=self.device)
+        if gda is None and want_dalong:
+            gda = torch.empty(self.params.n_pulses, dtype=self.rtype, device=self.device)
+        _lib.check(self.lib.tffr_entropy_step(self.handle, _ptr(samples), _ptr(phase), _ptr(dalong), _ptr(user_w),
+                                              _ptr(img), _ptr(loss), _ptr(gs), _ptr(gph), _ptr(gda),
+                                              _ptr(self.work), _stream()), "tffr_entropy_step")
+        return img, loss, gs, gph, gda
+
     def tffr_weights(self, out=None):
         shape = self.shape_samples
         if self.params.weighting == W_FFR:

@@ -83,8 +83,11 @@ def test_tffr_weights_and_kept_count(tau, mode, dtype):
     assert case.plan.tffr_kept_count() == int(kept.sum())
     # FP64: the closed forms cancel a(1 - e^{-a/2}) ~ a^2/2 out of terms of size a near
     # d = 0, a condition number ~ 2/a = 200, so two correct FP64 evaluations that round
-    # sin/cos differently agree to ~ 200 * 16 eps ~ 1e-12.  FP32: polynomial + rounding.
-    tol = 1e-12 if dtype == T.C128 else 3e-7
+    # sin/cos differently agree to ~ 200 * 16 eps ~ 1e-12; the kernels also form lam
+    # in a different order (a few ulp of lam ~ 3e4), which moves 1/g by |d(1/g)/dlam| <= 1
+    # times that.  FP32: polynomial + rounding.
+    lam_ulp = np.spacing(np.max(lam))
+    tol = 1e-12 + 8 * lam_ulp if dtype == T.C128 else 3e-7
     assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref)) + 1e-300
 
 
@@ -249,3 +252,64 @@ def test_nonsquare_image():
     got = case.plan.tffr_forward(st).cpu().numpy()
     assert got.shape == (48, 80)
     assert rel_l2(got, OP.image(case.prob, s)) < 1e-5
+
+
+# ---------------------------------------------------------------- fused step and graphs
+@pytest.mark.parametrize("dtype,width", [(T.C64, 7), (T.C128, 14)])
+def test_entropy_step_matches_separate_calls_and_oracle(dtype, width):
+    print(f"entropy step dtype={dtype}", flush=True)
+    case = Case(48, 160, 96, fov=60.0, dtype=dtype, width=width, seed=21)
+    s, st = case.samples()
+    phase = case.rng.normal(0, 0.5, 48)
+    dal = case.rng.normal(0, 0.004, 48)
+    ph, da = case.real(phase), case.real(dal)
+    img, loss, gs, gph, gda = case.plan.tffr_entropy_step(st, ph, da)
+    img2 = case.plan.tffr_forward(st, ph, da)
+    loss2, gI = case.plan.tffr_entropy(img2)
+    gs2, gph2, gda2 = case.plan.tffr_adjoint(gI, st, ph, da, want_phase=True, want_dalong=True)
+    assert torch.equal(img, img2)
+    assert abs(float(loss) - float(loss2)) < 1e-12 * abs(float(loss2))
+    tol = tol_for(case)
+    assert rel_l2(gs.cpu().numpy(), gs2.cpu().numpy()) < tol
+    assert rel_l2(gph.cpu().numpy(), gph2.cpu().numpy()) < 10 * tol
+    ref_img = OP.image(case.prob, s, case.rounded(phase), case.rounded(dal))
+    assert rel_l2(img.cpu().numpy(), ref_img) < tol
+    assert abs(float(loss) - OE.entropy(ref_img)) < 10 * tol * abs(OE.entropy(ref_img))
+    rgs, rgph, rgda = OP.backward(case.prob, OE.entropy_grad(ref_img), s, case.rounded(phase), case.rounded(dal))
+    assert rel_l2(gs.cpu().numpy(), rgs) < 20 * tol
+    assert np.max(np.abs(gph.cpu().numpy() - rgph)) < 20 * tol * np.max(np.abs(rgph))
+    assert np.max(np.abs(gda.cpu().numpy() - rgda)) < 20 * tol * np.max(np.abs(rgda))
+
+
+@pytest.mark.parametrize("weighting", [T.W_TFFR, T.W_FFR])
+def test_graph_replays_match_eager(weighting):
+    """The fused step captured in a HIP graph gives the eager result on every replay,
+    with other eager work and synchronisations between the replays."""
+    print(f"graph replay weighting={weighting}", flush=True)
+    case = Case(64, 128, 128, weighting=weighting, seed=22)
+    s, st = case.samples()
+    ph = case.real(case.rng.normal(0, 0.5, 64))
+    out = (torch.empty(case.plan.shape_image, dtype=case.ctype, device=DEV),
+           torch.empty((), dtype=torch.float64, device=DEV),
+           torch.empty(case.plan.shape_samples, dtype=case.ctype, device=DEV),
+           torch.empty(64, dtype=case.rtype, device=DEV), torch.empty(64, dtype=case.rtype, device=DEV))
+    eager = [t.clone() for t in case.plan.tffr_entropy_step(st, ph, out=out)]
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        case.plan.tffr_entropy_step(st, ph, out=out)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=side):
+            case.plan.tffr_entropy_step(st, ph, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        for t in out:
+            t.zero_()
+        case.plan.tffr_forward(st)  # unrelated eager work that reuses the workspace
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(out, eager):
+            assert torch.equal(a, b), f"replay {rep}"
