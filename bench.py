@@ -195,7 +195,15 @@ def main():
         for _ in range(args.profile_steps):
             step()
         torch.cuda.synchronize()
-        print(json.dumps({"profile_steps": args.profile_steps, "workload": wl.name}))
+        # calibration: a plain device copy of known size for the HBM byte counters
+        from paper_1910_10908_amd import profiling
+
+        src = torch.empty(profiling.COPY_BYTES, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_steps": args.profile_steps, "workload": wl.name,
+                          "copy_bytes": profiling.COPY_BYTES}))
         return
 
     ms, runner = time_step(torch, step, args.steps, args.warmup, graph=not args.eager)
@@ -212,17 +220,34 @@ def main():
     if not args.eager:
         ms_eager, _ = time_step(torch, step, max(10, args.steps // 4), 5, graph=False)
 
-    # dominant kernel: the range stage (one slice per workgroup), timed alone through the
-    # per-stage entry point with the same launch configuration as inside tffr_forward
+    # the two stage kernels, each timed alone through the per-stage entry points with the
+    # same launch configuration as inside tffr_forward; the slower one is reported
     hx = torch.empty((wl.n_pulses, wl.m), dtype=torch.complex64, device=dev)
+    img_k = torch.empty((wl.m, wl.m), dtype=torch.complex64, device=dev)
 
     def range_stage():
         T._lib.check(plan.lib.tffr_debug_rows(plan.handle, 1, T._ptr(s), T._ptr(ph), T._ptr(da), None,
                                               T._ptr(hx), T._stream()))
 
-    t_k = kernel_time(torch, range_stage)
-    alg_bytes = 8 * wl.n_samples + 8 * wl.n_pulses * wl.m  # read samples, write range spectra
+    def azimuth_stage():
+        T._lib.check(plan.lib.tffr_debug_cols(plan.handle, T._ptr(hx), T._ptr(img_k), T._stream()))
+
+    t_rows = kernel_time(torch, range_stage)
+    t_cols = kernel_time(torch, azimuth_stage)
+    # algorithmic bytes per launch: samples in + range spectra out; range spectra in + image out
+    bytes_rows = 8 * wl.n_samples + 8 * wl.n_pulses * wl.m
+    bytes_cols = 8 * wl.n_pulses * wl.m + 8 * wl.m * wl.m
+    if t_rows >= t_cols:
+        kname, t_k, alg_bytes = "k_fwd_rows", t_rows, bytes_rows
+    else:
+        kname, t_k, alg_bytes = "k_fwd_cols", t_cols, bytes_cols
     achieved = alg_bytes / t_k / 1e9
+    from paper_1910_10908_amd import profiling
+
+    tr = profiling.read_traffic(os.path.join(ROOT, "profiles", f"hbm_traffic_{kname}_{wl.name}.txt"))
+    traffic = None
+    if tr.get("source_hash") == profiling.kernel_source_hash() and "traffic_bytes" in tr:
+        traffic = float(tr["traffic_bytes"])
     kept = plan.tffr_kept_count()
 
     out = {
@@ -242,9 +267,9 @@ def main():
                    "fine_grid": list(plan.nfine), "kernel_width": width, "weighting": "tffr", "tau": 0.97,
                    "window_a": 0.01, "q": 3, "timing": "eager" if args.eager else "hip_graph",
                    "parallelism": "single_gpu"},
-        "roofline": {"bound": "hbm", "kernel": "k_fwd_rows (range stage, forward)", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel_us": t_k * 1e6, "alg_bytes": alg_bytes},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel_us": t_k * 1e6,
+                     "alg_bytes": alg_bytes, "stage_us": {"k_fwd_rows": t_rows * 1e6, "k_fwd_cols": t_cols * 1e6}},
         "kept_count": kept,
         "graph_replay_matches_eager": replay_ok,
         "eager_ms_per_step": ms_eager,

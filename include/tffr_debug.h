@@ -28,6 +28,11 @@ tffr_status tffr_debug_rows(tffr_plan *plan, int32_t stage, const void *d_sample
                             const void *d_phase, const void *d_dalong, const void *d_user_w,
                             void *d_out, tffr_stream stream);
 
+/* Azimuth stage of the forward path alone: d_hx [n_pulses][mx] range spectra (as
+ * tffr_debug_rows stage 1 returns them) -> d_image [mx][my].  Same launch as inside
+ * tffr_forward. */
+tffr_status tffr_debug_cols(tffr_plan *plan, const void *d_hx, void *d_image, tffr_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,7 @@ namespace {
 
 constexpr double kPi = 3.141592653589793;
 constexpr int kMaxLogN = 14;
-constexpr int kMaxHalfBand = 16;
+constexpr int kMaxHalfBand = 6;
 constexpr int kPartials = 1024;  // reduction blocks for the kept count
 constexpr int kEntropyParts = 256;  // reduction blocks for the entropy
 constexpr int kFuseStatsMax = 1024;  // entropy step: adjoint blocks reduce up to this many partials
@@ -567,11 +567,11 @@ tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double
   if (p->weighting == TFFR_W_FFR) {
     P->ffr_halfband = ffr_halfband(p, k, ku);
     g.band_b = P->ffr_halfband;
-    const size_t band = (size_t)p->n_pulses * p->n_freq * (2 * g.band_b + 1) * sizeof(double);
-    P->off_gband = off;
-    off = align_up(off + band);
-    P->off_zband = off;
-    off = align_up(off + band);
+    if ((size_t)p->n_freq * (2 * g.band_b + 1) * sizeof(double) > lds_max) return fail(TFFR_ERR_UNSUPPORTED);
+    const size_t N = (size_t)p->n_pulses * p->n_freq;
+    const size_t KT = 2 * ((size_t)std::ceil(p->q) + 1) + 1;
+    P->off_gband = off;  // FFR scratch: tap tables, floors, band, LU factors
+    off = align_up(off + N * (2 * KT + (2 * g.band_b + 1)) * sizeof(double) + N * sizeof(int));
   }
   P->work_bytes = off;
 
@@ -585,11 +585,11 @@ tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double
     hipError_t e = hipMemset(wb + P->off_status, 0, sizeof(int));
     if (e == hipSuccess) {
       if (P->dbl())
-        e = tffr::launch_ffr<double>(g, tables<double>(P), (double*)(wb + P->off_gband), (double*)(wb + P->off_zband),
-                                     (double*)P->ffr_d.p, (int*)(wb + P->off_status), 0);
+        e = tffr::launch_ffr<double>(g, tables<double>(P), (double*)(wb + P->off_gband), (double*)P->ffr_d.p,
+                                     (int*)(wb + P->off_status), 0);
       else
-        e = tffr::launch_ffr<float>(g, tables<float>(P), (double*)(wb + P->off_gband), (double*)(wb + P->off_zband),
-                                    (float*)P->ffr_d.p, (int*)(wb + P->off_status), 0);
+        e = tffr::launch_ffr<float>(g, tables<float>(P), (double*)(wb + P->off_gband), (float*)P->ffr_d.p,
+                                    (int*)(wb + P->off_status), 0);
     }
     int st = 0;
     if (e == hipSuccess) e = hipMemcpy(&st, wb + P->off_status, sizeof(int), hipMemcpyDeviceToHost);
@@ -668,10 +668,10 @@ tffr_status tffr_weights(tffr_plan* P, void* d_w, void* work, tffr_stream stream
   hipError_t e;
   if (P->prm.weighting == TFFR_W_FFR) {
     int* status = (int*)(wb + P->off_status);
-    e = P->dbl() ? tffr::launch_ffr<double>(P->geo, tables<double>(P), (double*)(wb + P->off_gband),
-                                            (double*)(wb + P->off_zband), (double*)d_w, status, st)
-                 : tffr::launch_ffr<float>(P->geo, tables<float>(P), (double*)(wb + P->off_gband),
-                                           (double*)(wb + P->off_zband), (float*)d_w, status, st);
+    e = P->dbl() ? tffr::launch_ffr<double>(P->geo, tables<double>(P), (double*)(wb + P->off_gband), (double*)d_w,
+                                            status, st)
+                 : tffr::launch_ffr<float>(P->geo, tables<float>(P), (double*)(wb + P->off_gband), (float*)d_w,
+                                           status, st);
   } else {
     unsigned long long* kept = (unsigned long long*)(wb + P->off_kept);
     e = P->dbl() ? tffr::launch_weights<double>(P->geo, tables<double>(P), (double*)d_w, kept, kPartials, st)
@@ -726,6 +726,16 @@ tffr_status tffr_debug_rows(tffr_plan* P, int32_t stage, const void* smp, const 
   hipStream_t st = (hipStream_t)stream;
   return P->dbl() ? do_forward<double>(P, smp, ph, da, uw, out, nullptr, st, stage)
                   : do_forward<float>(P, smp, ph, da, uw, out, nullptr, st, stage);
+}
+
+tffr_status tffr_debug_cols(tffr_plan* P, const void* hx, void* img, tffr_stream stream) {
+  if (!P || !hx || !img) return TFFR_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = P->dbl() ? tffr::launch_fwd_cols<double>(P->geo, tables<double>(P), P->cb, (const cplx<double>*)hx,
+                                                          (cplx<double>*)img, nullptr, st)
+                          : tffr::launch_fwd_cols<float>(P->geo, tables<float>(P), P->cb, (const cplx<float>*)hx,
+                                                         (cplx<float>*)img, nullptr, st);
+  return hip_status(e);
 }
 
 }  // extern "C"

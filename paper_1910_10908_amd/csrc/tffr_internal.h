@@ -80,8 +80,8 @@ hipError_t launch_weights(const Geo& g, const Tab<R>& t, R* w, unsigned long lon
                           int nblocks, hipStream_t st);
 hipError_t launch_sum_u64(const unsigned long long* parts, int n, long long* out, hipStream_t st);
 template <typename R>
-hipError_t launch_ffr(const Geo& g, const Tab<R>& t, double* gband, double* zband, R* dband,
-                      int* status, hipStream_t st);
+hipError_t launch_ffr(const Geo& g, const Tab<R>& t, double* scratch, R* dband, int* status,
+                      hipStream_t st);
 template <typename R>
 hipError_t launch_entropy(const Geo& g, const cplx<R>* img, double* partials, int nparts,
                           double* loss, cplx<R>* grad, hipStream_t st);

@@ -194,6 +194,15 @@ class Plan:
         return out
 
 
+def tffr_debug_cols(plan, hx, out=None):
+    """Azimuth stage of the forward path alone: range spectra [n_pulses][mx] -> image."""
+    plan._chk(hx, (plan.params.n_pulses, plan.params.mx), plan.ctype, "hx")
+    if out is None:
+        out = torch.empty(plan.shape_image, dtype=plan.ctype, device=plan.device)
+    _lib.check(plan.lib.tffr_debug_cols(plan.handle, _ptr(hx), _ptr(out), _stream()), "tffr_debug_cols")
+    return out
+
+
 def tffr_debug_fft(x, sign):
     """Batched LDS FFT of the rows of x (complex64/complex128, power-of-two length)."""
     lib = _lib.load()
