@@ -140,7 +140,8 @@ struct tffr_plan {
   // device tables
   DevBuf k, ku, ky, ystart, ytap, deapx, deapy, twx, twy, poly, ffr_d, ycn, ycw;
   // workspace layout
-  size_t off_hx = 0, off_part = 0, off_stats = 0, off_kept = 0, off_count = 0, off_status = 0, off_gband = 0, off_zband = 0,
+  bool ent_fused = false;  // entropy step uses the fused azimuth kernel
+  size_t off_hx = 0, off_h2 = 0, off_cblk = 0, off_part = 0, off_stats = 0, off_kept = 0, off_count = 0, off_status = 0, off_gband = 0, off_zband = 0,
          off_dband = 0, work_bytes = 0;
   bool dbl() const { return prm.dtype == TFFR_C128; }
   size_t csize() const { return dbl() ? 16 : 8; }
@@ -299,7 +300,7 @@ tffr_status do_adjoint(tffr_plan* P, const void* cot, const void* smp, const voi
   hipError_t e = tffr::launch_adj_cols<R>(P->geo, t, P->cb, (const cplx<R>*)cot, hx, nullptr, nullptr, 0, nullptr, st);
   if (e == hipSuccess)
     e = tffr::launch_adj_rows<R>(P->geo, t, sample_type(P), hx, smp, (const R*)ph, (const R*)da, w, (cplx<R>*)gs,
-                                 (R*)gph, (R*)gda, st);
+                                 (R*)gph, (R*)gda, tffr::EntComb<R>{}, st);
   return hip_status(e);
 }
 
@@ -314,17 +315,41 @@ tffr_status do_entropy_step(tffr_plan* P, const void* smp, const void* ph, const
   double* part = (double*)(wb + P->off_part);
   double* stats = (double*)(wb + P->off_stats);
   const int nparts = (P->prm.mx + P->cb - 1) / P->cb;
+  cplx<R>* h2 = (cplx<R>*)(wb + P->off_h2);
+  R* cblk = (R*)(wb + P->off_cblk);
+  // range stage; azimuth forward + entropy sums + adjoint azimuth transforms of the two
+  // gradient fields in one kernel (h1 overwrites the range spectra in place); range
+  // adjoint combining the fields with the global entropy sums
   hipError_t e = tffr::launch_fwd_rows<R>(P->geo, t, sample_type(P), smp, (const R*)ph, (const R*)da, w, hx, 1, st);
-  if (e == hipSuccess) e = tffr::launch_fwd_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, part, st);
   // few partial sums: every adjoint block reduces them itself (no separate launch)
   const bool fuse = nparts <= kFuseStatsMax;
+  if (!P->ent_fused) {  // the fused azimuth kernel's LDS does not fit: image round trip
+    if (e == hipSuccess) e = tffr::launch_fwd_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, part, st);
+    if (e == hipSuccess && !fuse) e = tffr::launch_entropy_stats(part, nparts, stats, loss, st);
+    if (e == hipSuccess)
+      e = fuse ? tffr::launch_adj_cols<R>(P->geo, t, P->cb, (const cplx<R>*)img, hx, nullptr, part, nparts, loss, st)
+               : tffr::launch_adj_cols<R>(P->geo, t, P->cb, (const cplx<R>*)img, hx, stats, nullptr, 0, nullptr, st);
+    if (e == hipSuccess)
+      e = tffr::launch_adj_rows<R>(P->geo, t, sample_type(P), hx, smp, (const R*)ph, (const R*)da, w, (cplx<R>*)gs,
+                                   (R*)gph, (R*)gda, tffr::EntComb<R>{}, st);
+    return hip_status(e);
+  }
+  if (e == hipSuccess) e = tffr::launch_ent_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, part, cblk, hx, h2, st);
   if (e == hipSuccess && !fuse) e = tffr::launch_entropy_stats(part, nparts, stats, loss, st);
-  if (e == hipSuccess)
-    e = fuse ? tffr::launch_adj_cols<R>(P->geo, t, P->cb, (const cplx<R>*)img, hx, nullptr, part, nparts, loss, st)
-             : tffr::launch_adj_cols<R>(P->geo, t, P->cb, (const cplx<R>*)img, hx, stats, nullptr, 0, nullptr, st);
+  tffr::EntComb<R> ec{};
+  ec.h2 = h2;
+  ec.cblk = cblk;
+  ec.cb = P->cb;
+  if (fuse) {
+    ec.partials = part;
+    ec.nparts = nparts;
+    ec.loss = loss;
+  } else {
+    ec.stats = stats;
+  }
   if (e == hipSuccess)
     e = tffr::launch_adj_rows<R>(P->geo, t, sample_type(P), hx, smp, (const R*)ph, (const R*)da, w, (cplx<R>*)gs,
-                                 (R*)gph, (R*)gda, st);
+                                 (R*)gph, (R*)gda, ec, st);
   return hip_status(e);
 }
 
@@ -333,15 +358,28 @@ bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 // Range gridding schedule (see k_fwd_rows): S = samples a thread owns so that samples S
 // apart are more than W fine cells apart, and the part length so that no part of a
 // slice spans the fine row (after wrapping, two samples of a part never share cells).
-void range_schedule(const tffr_params* p, const double* k, const double* ku, int nfx, int* S, int* part_len) {
+// Range gridding schedule.  U = kx fov_x nfx / (2 pi mx) is a sample's unwrapped fine
+// cell coordinate.  S (samples per thread run / per sub-pass group) satisfies
+// S * (smallest spacing of U) > W + 1, one cell of margin over the W-cell tap span, so
+// the taps of samples S apart never meet even when a fraction rounds across a cell
+// boundary.  Slices are cut into parts whose span (plus taps) stays inside the fine row.
+// The sliding-window kernel (mode 1) serves dense slices, where consecutive samples are
+// under kDenseSpacing cells apart; each of its threads takes at most one run per part.
+constexpr double kDenseSpacing = 2.5;
+
+void range_schedule(const tffr_params* p, const double* k, const double* ku, int nfx, int nt, int* S, int* part_len,
+                    int* mode) {
   const double tx = p->fov_x / (2.0 * kPi * p->mx);
   const int P = p->n_freq, W = p->kernel_width;
-  double smin = 1e300;
+  double smin = 1e300, smax = 0.0;
   int Q = 1;
   std::vector<double> U(P);
   for (int n = 0; n < p->n_pulses; ++n) {
     for (int i = 0; i < P; ++i) U[i] = std::sqrt(4.0 * (k[i] * k[i]) - ku[n] * ku[n]) * tx * nfx;
-    for (int i = 0; i + 1 < P; ++i) smin = std::min(smin, U[i + 1] - U[i]);
+    for (int i = 0; i + 1 < P; ++i) {
+      smin = std::min(smin, U[i + 1] - U[i]);
+      smax = std::max(smax, U[i + 1] - U[i]);
+    }
     for (;; ++Q) {
       const int len = (P + Q - 1) / Q;
       bool ok = true;
@@ -355,10 +393,18 @@ void range_schedule(const tffr_params* p, const double* k, const double* ku, int
   int s = 1;
   if (P > 1) {
     const double sm = smin * (1.0 - 1e-9);
-    s = (int)std::min<double>((double)P, std::floor(W / sm) + 1.0);
+    s = (int)std::min<double>((double)P, std::floor((W + 1.0) / sm) + 1.0);
   }
   *S = std::max(1, s);
-  *part_len = (P + Q - 1) / Q;
+  int m = (P > 1 && W <= tffr::kRunWindow && smax < kDenseSpacing) ? 1 : 0;
+  if (const char* e = std::getenv("TFFR_RANGE_MODE")) {
+    const int v = std::atoi(e);
+    if (v == 0 || (v == 1 && W <= tffr::kRunWindow)) m = v;
+  }
+  *mode = m;
+  int len = (P + Q - 1) / Q;
+  if (m == 1) len = std::min(len, nt * *S);
+  *part_len = len;
 }
 
 }  // namespace
@@ -453,6 +499,10 @@ tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double
     if ((v == 1 || v == 2 || v == 4) && cols_lds(v) <= lds_max) cb = v;
   }
   P->cb = cb;
+  // entropy step: the fused azimuth kernel holds [CB][nfy] image columns plus, in the
+  // staged-spectra space, at least [CB][nfy] more
+  P->ent_fused = ((size_t)nfy * cb + std::max<size_t>((size_t)p->n_pulses * cb, (size_t)nfy * cb) + twy_n) * csz <=
+                 lds_max;
 
   tffr::Geo& g = P->geo;
   g.n_pulses = p->n_pulses;
@@ -506,12 +556,12 @@ tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double
   for (int n = 0; n < p->n_pulses; ++n)
     for (int i = 0; i < W; ++i) {
       const int cell = (((ys[n] + i) % nfy) + nfy) % nfy;
-      const size_t slot = (size_t)cell * yemax + ccount[cell]++;
+      const size_t slot = (size_t)(ccount[cell]++) * nfy + cell;
       cn[slot] = n;
       cw[slot] = taps[(size_t)n * W + i];
     }
   g.yemax = yemax;
-  range_schedule(p, k, ku, nfx, &g.sub, &g.part_len);
+  range_schedule(p, k, ku, nfx, tffr::rows_threads(lognx), &g.sub, &g.part_len, &g.range_mode);
   std::vector<double> dx = deapod_table(p->mx, nfx, W, P->beta), dy = deapod_table(p->my, nfy, W, P->beta);
   std::vector<double> twx = twiddle_table(nfx), twy = twiddle_table(nfy);
   if (P->dbl()) {
@@ -554,6 +604,10 @@ tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double
   size_t off = 0;
   P->off_hx = off;
   off = align_up(off + (size_t)p->n_pulses * p->mx * csz);
+  P->off_h2 = off;  // entropy step: second gradient field of the range spectra
+  off = align_up(off + (size_t)p->n_pulses * p->mx * csz);
+  P->off_cblk = off;  // entropy step: centring constant per column block
+  off = align_up(off + (P->dbl() ? sizeof(double) : sizeof(float)) * (size_t)((p->mx + P->cb - 1) / P->cb));
   P->off_part = off;
   off = align_up(off + sizeof(double) * 2 * std::max<size_t>(kEntropyParts, (p->mx + P->cb - 1) / P->cb));
   P->off_stats = off;

@@ -26,6 +26,7 @@ struct Geo {
   int32_t use_poly, nseg, deg;  // tFFR weight polynomial (float path)
   int32_t sub;                  // range gridding: samples per thread per sub-pass group
   int32_t part_len;             // range gridding: samples per part (part span < fine row)
+  int32_t range_mode;           // range gridding: 0 sub-passes, 1 sliding-window runs (dense slices)
   int32_t yemax;                // azimuth gridding: most (slice, tap) pairs reaching one cell
   int32_t keep0;                // threshold decision for a sample exactly on the lattice
   double beta;                  // ES kernel shape
@@ -58,6 +59,21 @@ struct Tab {
 
 enum SampleType { ST_C64 = 0, ST_C128 = 1, ST_H2 = 2 };
 
+// Entropy-step input of the range adjoint: with h2 non-null its range-spectra cotangent
+// is alpha h1 + (beta + alpha cblk[column / cb]) h2 (h1 is the usual hx argument), where
+// alpha, beta come from the global entropy sums: reduced by every block from nparts
+// partial pairs (then block 0 writes *loss), or read from stats = {S, E}.
+template <typename R>
+struct EntComb {
+  const cplx<R>* h2;
+  const R* cblk;
+  int cb;
+  const double* partials;
+  int nparts;
+  const double* stats;
+  double* loss;
+};
+
 // Launchers (tffr_kernels.hip).  All enqueue on `st` and return the launch status.
 template <typename R>
 hipError_t launch_fwd_rows(const Geo& g, const Tab<R>& t, int stype, const void* samples,
@@ -72,9 +88,13 @@ hipError_t launch_adj_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>*
                            double* loss, hipStream_t st);
 hipError_t launch_entropy_stats(const double* partials, int nparts, double* stats, double* loss, hipStream_t st);
 template <typename R>
+hipError_t launch_ent_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>* hx, cplx<R>* img,
+                           double* partials, R* cblk, cplx<R>* h1, cplx<R>* h2, hipStream_t st);
+template <typename R>
 hipError_t launch_adj_rows(const Geo& g, const Tab<R>& t, int stype, const cplx<R>* hx,
                            const void* samples, const R* phase, const R* dalong, const R* w,
-                           cplx<R>* grad_s, R* grad_phase, R* grad_dalong, hipStream_t st);
+                           cplx<R>* grad_s, R* grad_phase, R* grad_dalong, const EntComb<R>& ec,
+                           hipStream_t st);
 template <typename R>
 hipError_t launch_weights(const Geo& g, const Tab<R>& t, R* w, unsigned long long* kept_partial,
                           int nblocks, hipStream_t st);
@@ -90,5 +110,7 @@ hipError_t launch_fft(int log2n, int batch, int sign, const cplx<R>* in, cplx<R>
                       const cplx<R>* tw, hipStream_t st);
 
 size_t max_dynamic_lds();  // bytes of LDS one workgroup may use on this device
+int rows_threads(int logn);  // threads per workgroup of the range-stage kernels for a 2^logn fine row
+constexpr int kRunWindow = 8;  // register window of the sliding-window range kernel (widths up to 8)
 
 }  // namespace tffr

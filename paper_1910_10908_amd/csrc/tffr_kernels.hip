@@ -164,13 +164,24 @@ __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* tw) {
       const int col = bf / NB, i = bf - col * NB;
       const int k = i & (P - 1);
       if constexpr (P > 1) {
+        // one table lookup w = exp(SIGN 2 pi i k / (P RAD)); the other powers by
+        // products of depth <= 3 (w^2 = w w, w^3 = w^2 w, w^4 = w^2 w^2, ...)
         constexpr int STEP = N / (P * RAD);
-#pragma unroll
-        for (int r = 1; r < RAD; ++r) {
-          cplx<R> w = twiddle<N>(tw, r * k * STEP);
-          if (SIGN < 0) w.y = -w.y;
-          v[b][r] = cmul(v[b][r], w);
+        cplx<R> wp[RAD];
+        wp[1] = twiddle<N>(tw, k * STEP);
+        if (SIGN < 0) wp[1].y = -wp[1].y;
+        if constexpr (RAD >= 4) {
+          wp[2] = cmul(wp[1], wp[1]);
+          wp[3] = cmul(wp[2], wp[1]);
         }
+        if constexpr (RAD == 8) {
+          wp[4] = cmul(wp[2], wp[2]);
+          wp[5] = cmul(wp[4], wp[1]);
+          wp[6] = cmul(wp[3], wp[3]);
+          wp[7] = cmul(wp[4], wp[3]);
+        }
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) v[b][r] = cmul(v[b][r], wp[r]);
       }
       dft<SIGN, RAD>(v[b]);
       const int j = (i - k) * RAD + k;
@@ -484,16 +495,219 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(Geo g, Tab<R> t, int stype, con
   }
 }
 
+// Range stage for densely sampled slices (the plan's choice when consecutive samples sit
+// well under W fine cells apart).  Thread t takes the run of S consecutive samples
+// p0 = part start + S t ... and slides a window of W register accumulators along the
+// fine row: a sample whose first tap cell is c0 first retires the window cells below c0
+// (in increasing cell order), then adds its W taps to the window at fixed register
+// positions.  With S * (smallest sample spacing) > W, the first W cells a run retires
+// (its "lead") are the only cells another run (the previous one) also reaches, so
+// every other retired cell is read-add-written into LDS at once without conflict; the
+// lead cells are kept in registers and added after one barrier, when no other run
+// writes.  Two barriers per part instead of one per sample of a run.
+template <typename R, int LOGN, int NT, int WM>
+__global__ __launch_bounds__(NT) void k_fwd_rows_run(Geo g, Tab<R> t, int stype, const void* __restrict__ samples,
+                                                     const R* __restrict__ phase, const R* __restrict__ dalong,
+                                                     const R* __restrict__ w, cplx<R>* __restrict__ out,
+                                                     int stage) {
+  constexpr int N = 1 << LOGN;
+  constexpr int DPT = (N + NT - 1) / NT;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
+  cplx<R>* buf = tw + tw_entries<N>();
+  float* lpoly = reinterpret_cast<float*>(buf + N);
+  const int n = blockIdx.x;
+  const bool ffr = g.weighting == 2;
+  const int S = g.sub, W = g.W, plen = g.part_len;
+  const size_t base_s = (size_t)n * g.n_freq;
+  load_twiddles<N, NT>(tw, t.twx);
+  const float* poly = load_poly<NT>(g, t.poly, lpoly);
+  for (int i = threadIdx.x; i < N; i += NT) buf[i] = {0, 0};
+  const cplx<R> rot = row_rotation(t, phase, dalong, n);
+  const double ku = t.ku[n];
+  const R halfw = (R)(0.5 * g.W), inv_halfw = (R)(2.0 / g.W), beta = es_shape<R>(g);
+  __syncthreads();  // row zeroed, tables in LDS
+  for (int pa = 0; pa < g.n_freq; pa += plen) {
+    const int pb = min(pa + plen, g.n_freq);
+    const int p0 = pa + S * (int)threadIdx.x;
+    const int p1 = min(p0 + S, pb);
+    cplx<R> acc[WM], lead[WM];
+#pragma unroll
+    for (int i = 0; i < WM; ++i) acc[i] = lead[i] = cplx<R>{0, 0};
+    int base = 0, cfirst = 0;
+    // retire the lowest window cell: into the lead registers if it is one of the run's
+    // first W cells, else straight into the row; then shift the window down one cell
+    auto retire = [&]() {
+      if (base - cfirst < W) {
+#pragma unroll
+        for (int i = 0; i + 1 < WM; ++i) lead[i] = lead[i + 1];
+        lead[WM - 1] = acc[0];
+      } else {
+        cplx<R>& bb = buf[base & (N - 1)];
+        bb = bb + acc[0];
+      }
+#pragma unroll
+      for (int i = 0; i + 1 < WM; ++i) acc[i] = acc[i + 1];
+      acc[WM - 1] = cplx<R>{0, 0};
+      ++base;
+    };
+    double k_nx = p0 < p1 ? t.k[p0] : 0.0;
+    cplx<R> s_nx = (p0 < p1 && !ffr) ? load_sample<R>(samples, stype, base_s + p0) : cplx<R>{0, 0};
+    for (int p = p0; p < p1; ++p) {
+      const double kp = k_nx;
+      const cplx<R> sp = s_nx;
+      if (p + 1 < p1) {
+        k_nx = t.k[p + 1];
+        if (!ffr) s_nx = load_sample<R>(samples, stype, base_s + p + 1);
+      }
+      const double kx = stolt_kx(kp, ku);
+      const double lam = lattice_coord(kx, g);
+      const cplx<R> c = weighted_sample<R>(g, t, poly, stype, samples, w, n, p, ku, lam, rot, sp);
+      const double tt = kx * g.tx_scale;
+      int ui;
+      R f;
+      fine_pos<R>(tt, N, ui, f);
+      const int k0 = (int)ceil(f - halfw);
+      // unwrapped first tap cell (only differences and the low LOGN bits are used)
+      const int c0 = (int)((unsigned)floor(tt) * (unsigned)N + (unsigned)(ui + k0));
+      if (p == p0) base = cfirst = c0;
+      for (int adv = c0 - base; adv > 0; --adv) retire();
+      const R z0 = ((R)k0 - f) * inv_halfw;
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        if (i < W) {
+          const R phi = es_kernel(z0 + (R)i * inv_halfw, beta);
+          acc[i] = acc[i] + phi * c;
+        }
+      }
+    }
+    if (p0 < p1)
+      for (int i = 0; i < W; ++i) retire();
+    __syncthreads();
+    if (p0 < p1) {
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        if (i >= WM - W) {
+          cplx<R>& bb = buf[(cfirst + i - (WM - W)) & (N - 1)];
+          bb = bb + lead[i];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (stage == 0) {
+    for (int i = threadIdx.x; i < N; i += NT) out[(size_t)n * N + i] = buf[i];
+    return;
+  }
+  const int mx = g.mx;
+  R dx[DPT];
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) {
+    const int jx = threadIdx.x + j * NT;
+    dx[j] = jx < mx ? t.deapx[jx] : (R)0;
+  }
+  lds_fft<+1, N, NT>(buf, tw);
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) {
+    const int jx = threadIdx.x + j * NT;
+    if (jx < mx) out[(size_t)n * mx + jx] = dx[j] * buf[(jx - mx / 2) & (N - 1)];
+  }
+}
+
+// ---------------------------------------------------------------------------- azimuth helpers
+// The plan's azimuth cell table, entry e of fine cell iy at e * N + iy: the e-th (slice,
+// tap) pair reaching the cell (padded with slice 0, tap 0).  A thread owns the cells
+// threadIdx.x + j NT; its entries of one e are loaded together (coalesced over lanes).
+template <typename R, int N, int NT>
+struct CellEntries {
+  int32_t n[N / NT];
+  R w[N / NT];
+};
+template <typename R, int N, int NT>
+__device__ __forceinline__ void load_entries(const Tab<R>& t, int e, CellEntries<R, N, NT>& ce) {
+#pragma unroll
+  for (int j = 0; j < N / NT; ++j) {
+    const size_t i = (size_t)e * N + threadIdx.x + j * NT;
+    ce.n[j] = t.ycell_n[i];
+    ce.w[j] = t.ycell_w[i];
+  }
+}
+
+// Stage the block's CB columns of the range spectra in LDS as hs[n][c] (zeros past the
+// last column of the image).
+template <typename R, int NT, int CB>
+__device__ __forceinline__ void stage_spectra(const Geo& g, const cplx<R>* __restrict__ hx, cplx<R>* hs, int c0,
+                                              int ncol) {
+  const int total = g.n_pulses * CB;
+  for (int idx = threadIdx.x; idx < total; idx += NT) {
+    const int nn = idx / CB, c = idx - nn * CB;
+    hs[idx] = c < ncol ? hx[(size_t)nn * g.mx + c0 + c] : cplx<R>{0, 0};
+  }
+}
+
+// Azimuth gridding of CB columns: every fine cell gathers its (slice, tap) pairs from the
+// staged spectra (no atomics); buf[c][iy].  `cur` holds the thread's entries e = 0, and
+// the entries e + 1 are loaded while those of e are applied.
+template <typename R, int N, int NT, int CB>
+__device__ __forceinline__ void cols_gather(const Geo& g, const Tab<R>& t, CellEntries<R, N, NT> cur,
+                                            const cplx<R>* hs, cplx<R>* buf) {
+  constexpr int CPT = N / NT;
+  cplx<R> acc[CPT][CB];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j)
+#pragma unroll
+    for (int c = 0; c < CB; ++c) acc[j][c] = {0, 0};
+  const int E = g.yemax;
+  for (int e = 0; e < E; ++e) {
+    CellEntries<R, N, NT> nx = cur;
+    if (e + 1 < E) load_entries(t, e + 1, nx);
+#pragma unroll
+    for (int j = 0; j < CPT; ++j)
+#pragma unroll
+      for (int c = 0; c < CB; ++c) acc[j][c] = acc[j][c] + cur.w[j] * hs[cur.n[j] * CB + c];
+    cur = nx;
+  }
+#pragma unroll
+  for (int j = 0; j < CPT; ++j)
+#pragma unroll
+    for (int c = 0; c < CB; ++c) buf[c * N + threadIdx.x + j * NT] = acc[j][c];
+}
+
+// Azimuth interpolation (type 2) of NC fine columns buf[c][.] at every slice: the W taps
+// of slice n are loaded once and applied to all NC columns; out[c][n] gets column c.
+template <typename R, int N, int NT, int NC>
+__device__ __forceinline__ void cols_interp(const Geo& g, const Tab<R>& t, const cplx<R>* buf, int nc_valid,
+                                            cplx<R>* const* out, int c_stride, int c0) {
+  const int W = g.W;
+  for (int nn = threadIdx.x; nn < g.n_pulses; nn += NT) {
+    const int ys = t.ystart[nn];
+    const R* tap = t.ytap + (size_t)nn * W;
+    cplx<R> acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = {0, 0};
+    for (int i = 0; i < W; ++i) {
+      const R tp = tap[i];
+      const int cell = (ys + i) & (N - 1);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[c] = acc[c] + tp * buf[c * N + cell];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if ((c % c_stride) < nc_valid) out[c / c_stride][(size_t)nn * g.mx + c0 + (c % c_stride)] = acc[c];
+  }
+}
+
 // Azimuth stage: CB range columns per workgroup.  The block's columns of the range
-// spectra are staged in LDS; every fine azimuth cell then gathers its (slice, tap) pairs
-// from the plan's padded cell table for all CB columns at once (no atomics), batched
-// inverse FFT along azimuth, keep the centred my bins, divide by the kernel transform,
-// write the image columns (range-major).  With partials non-null the block also writes
-// its share of the image-entropy sums (sum |I|^2, sum |I|^2 ln |I|^2).
+// spectra are staged in LDS; every fine azimuth cell gathers its (slice, tap) pairs for
+// all CB columns at once (no atomics), batched inverse FFT along azimuth, keep the
+// centred my bins, divide by the kernel transform, write the image columns
+// (range-major).  With partials non-null the block also writes its share of the
+// image-entropy sums (sum |I|^2, sum |I|^2 ln |I|^2).
 template <typename R, int LOGN, int NT, int CB>
 __global__ __launch_bounds__(NT) void k_fwd_cols(Geo g, Tab<R> t, const cplx<R>* __restrict__ hx,
                                                  cplx<R>* __restrict__ img, double* __restrict__ partials) {
   constexpr int N = 1 << LOGN;
+  constexpr int DPT = N / NT;
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
   cplx<R>* buf = tw + tw_entries<N>();
@@ -501,43 +715,39 @@ __global__ __launch_bounds__(NT) void k_fwd_cols(Geo g, Tab<R> t, const cplx<R>*
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int c0 = lb * CB;
   const int ncol = min(CB, g.mx - c0);
+  const int my = g.my;
+  CellEntries<R, N, NT> ce;
+  load_entries(t, 0, ce);
   load_twiddles<N, NT>(tw, t.twy);
-  const int total = g.n_pulses * CB;
-  for (int idx = threadIdx.x; idx < total; idx += NT) {
-    const int nn = idx / CB, c = idx - nn * CB;
-    hs[idx] = c < ncol ? hx[(size_t)nn * g.mx + c0 + c] : cplx<R>{0, 0};
+  stage_spectra<R, NT, CB>(g, hx, hs, c0, ncol);
+  R dy[DPT];
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) {
+    const int jy = threadIdx.x + j * NT;
+    dy[j] = jy < my ? t.deapy[jy] : (R)0;
   }
   __syncthreads();
-  const int E = g.yemax;
-  for (int iy = threadIdx.x; iy < N; iy += NT) {
-    cplx<R> acc[CB];
-#pragma unroll
-    for (int c = 0; c < CB; ++c) acc[c] = {0, 0};
-    const int32_t* en = t.ycell_n + (size_t)iy * E;
-    const R* ew = t.ycell_w + (size_t)iy * E;
-    for (int e = 0; e < E; ++e) {
-      const int nn = en[e];
-      const R wt = ew[e];
-#pragma unroll
-      for (int c = 0; c < CB; ++c) acc[c] = acc[c] + wt * hs[nn * CB + c];
-    }
-#pragma unroll
-    for (int c = 0; c < CB; ++c) buf[c * N + iy] = acc[c];
-  }
+  cols_gather<R, N, NT, CB>(g, t, ce, hs, buf);
   __syncthreads();
   lds_fft<+1, N, NT, CB>(buf, tw);
-  const int my = g.my;
   double es = 0.0, et = 0.0;
-  for (int c = 0; c < ncol; ++c) {
-    const cplx<R>* col = buf + c * N;
-    cplx<R>* o = img + (size_t)(c0 + c) * my;
-    for (int jy = threadIdx.x; jy < my; jy += NT) {
-      const cplx<R> v = t.deapy[jy] * col[(jy - my / 2) & (N - 1)];
-      o[jy] = v;
-      if (partials) {
-        const R a = v.x * v.x + v.y * v.y;
-        es += (double)a;
-        if (a > (R)0) et += (double)(a * log(a));
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    if (c < ncol) {
+      const cplx<R>* col = buf + c * N;
+      cplx<R>* o = img + (size_t)(c0 + c) * my;
+#pragma unroll
+      for (int j = 0; j < DPT; ++j) {
+        const int jy = threadIdx.x + j * NT;
+        if (jy < my) {
+          const cplx<R> v = dy[j] * col[(jy - my / 2) & (N - 1)];
+          o[jy] = v;
+          if (partials) {
+            const R a = v.x * v.x + v.y * v.y;
+            es += (double)a;
+            if (a > (R)0) et += (double)(a * log(a));
+          }
+        }
       }
     }
   }
@@ -549,6 +759,96 @@ __global__ __launch_bounds__(NT) void k_fwd_cols(Geo g, Tab<R> t, const cplx<R>*
       partials[2 * lb + 1] = et;
     }
   }
+}
+
+// Entropy step, azimuth stage forward and backward in one pass per column block.  The
+// entropy gradient is linear in two local fields,
+//   dE/dI = -(2/S)(ln|I|^2 - ln S + E) I = alpha I (ln|I|^2 - cc) + (beta + alpha cc) I,
+// alpha = -2/S, beta = 2 T / S^2 (S = sum |I|^2, T = sum |I|^2 ln |I|^2 over the whole
+// image, E = ln S - T/S), for any constant cc.  So the block, right after forming its
+// image columns (written out, with its entropy partial sums), takes the adjoint azimuth
+// transform of both fields, I (ln|I|^2 - cc) -> h1 and I -> h2, with cc = ln of the
+// block's mean |I|^2 (keeps the first field centred; stored in cblk), and the range
+// adjoint combines alpha h1 + (beta + alpha cc) h2 once the global sums are known.
+// LDS: the two fields' fine columns [2][CB][N] reuse the staged-spectra space.  h1 may
+// be hx itself: a block reads only its own columns of hx, all before its first write.
+template <typename R, int LOGN, int NT, int CB>
+__global__ __launch_bounds__(NT) void k_ent_cols(Geo g, Tab<R> t, const cplx<R>* hx, cplx<R>* __restrict__ img,
+                                                 double* __restrict__ partials, R* __restrict__ cblk, cplx<R>* h1,
+                                                 cplx<R>* __restrict__ h2) {
+  constexpr int N = 1 << LOGN;
+  constexpr int DPT = N / NT;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
+  cplx<R>* buf = tw + tw_entries<N>();  // [CB][N]: image field I, then its transform
+  cplx<R>* hs = buf + (size_t)CB * N;   // staged spectra; afterwards [CB][N] the field I (ln|I|^2 - cc)
+  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int c0 = lb * CB;
+  const int ncol = min(CB, g.mx - c0);
+  const int my = g.my;
+  CellEntries<R, N, NT> ce;
+  load_entries(t, 0, ce);
+  load_twiddles<N, NT>(tw, t.twy);
+  stage_spectra<R, NT, CB>(g, hx, hs, c0, ncol);
+  __syncthreads();
+  cols_gather<R, N, NT, CB>(g, t, ce, hs, buf);
+  __syncthreads();
+  lds_fft<+1, N, NT, CB>(buf, tw);
+  // image pixels: thread owns fine bins i = threadIdx.x + j NT (pixel jy = signed(i) + my/2)
+  double es = 0.0, et = 0.0;
+  cplx<R> v[CB][DPT];
+  R lg[CB][DPT], dyv[DPT];
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) {
+    const int i = threadIdx.x + j * NT;
+    const int jy = (i < N / 2 ? i : i - N) + my / 2;
+    dyv[j] = (jy >= 0 && jy < my) ? t.deapy[jy] : (R)0;
+  }
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+      const int i = threadIdx.x + j * NT;
+      const int jy = (i < N / 2 ? i : i - N) + my / 2;
+      v[c][j] = {0, 0};
+      lg[c][j] = 0;
+      if (c < ncol && jy >= 0 && jy < my) {
+        const cplx<R> x = dyv[j] * buf[c * N + i];
+        img[(size_t)(c0 + c) * my + jy] = x;
+        const R a = x.x * x.x + x.y * x.y;
+        es += (double)a;
+        if (a > (R)0) {
+          lg[c][j] = log(a);
+          et += (double)(a * lg[c][j]);
+          v[c][j] = x;
+        }
+      }
+    }
+  }
+  es = block_sum<NT>(es);  // (its barriers also end every read of buf and hs above)
+  et = block_sum<NT>(et);
+  const double npix = (double)ncol * (double)my;
+  const R cc = es > 0.0 ? (R)log(es / npix) : (R)0;
+  if (threadIdx.x == 0) {
+    partials[2 * lb] = es;
+    partials[2 * lb + 1] = et;
+    cblk[lb] = cc;
+  }
+  // adjoint fields, deapodised and zero-padded on the fine grid (same bins as above)
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+      const int i = threadIdx.x + j * NT;
+      const cplx<R> x = dyv[j] * v[c][j];
+      buf[c * N + i] = x;
+      hs[c * N + i] = (lg[c][j] - cc) * x;
+    }
+  }
+  __syncthreads();
+  lds_fft<-1, N, NT, 2 * CB>(buf, tw);  // buf and hs are contiguous: 2 CB columns
+  cplx<R>* outs[2] = {h2, h1};
+  cols_interp<R, N, NT, 2 * CB>(g, t, buf, ncol, outs, CB, c0);
 }
 
 // Image entropy from the per-block sums: E = ln S - (1/S) sum a ln a.  One block.
@@ -626,17 +926,8 @@ __global__ __launch_bounds__(NT) void k_adj_cols(Geo g, Tab<R> t, const cplx<R>*
   }
   __syncthreads();
   lds_fft<-1, N, NT, CB>(buf, tw);
-  const int W = g.W;
-  const int total = g.n_pulses * ncol;
-  for (int idx = threadIdx.x; idx < total; idx += NT) {
-    const int nn = idx / ncol, c = idx - nn * ncol;
-    const int ys = t.ystart[nn];
-    const R* tap = t.ytap + (size_t)nn * W;
-    const cplx<R>* col = buf + c * N;
-    cplx<R> acc = {0, 0};
-    for (int i = 0; i < W; ++i) acc = acc + tap[i] * col[(ys + i) & (N - 1)];
-    hx[(size_t)nn * g.mx + c0 + c] = acc;
-  }
+  cplx<R>* outs[1] = {hx};
+  cols_interp<R, N, NT, CB>(g, t, buf, ncol, outs, CB, c0);
 }
 
 // Range stage, type 2: per slice, divide by the kernel transform, zero-pad, forward FFT
@@ -649,7 +940,7 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
                                                  const void* __restrict__ samples, const R* __restrict__ phase,
                                                  const R* __restrict__ dalong, const R* __restrict__ w,
                                                  cplx<R>* __restrict__ grad_s, R* __restrict__ grad_phase,
-                                                 R* __restrict__ grad_dalong) {
+                                                 R* __restrict__ grad_dalong, EntComb<R> ec) {
   constexpr int N = 1 << LOGN;
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
@@ -669,10 +960,40 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
   load_twiddles<N, NT>(tw, t.twx);
   const float* poly = load_poly<NT>(g, t.poly, lpoly);
   const cplx<R>* in = hx + (size_t)n * mx;
-  for (int i = threadIdx.x; i < N; i += NT) {
-    const int jp = i < N / 2 ? i : i - N;
-    const int jx = jp + mx / 2;
-    buf[i] = (jx >= 0 && jx < mx) ? t.deapx[jx] * in[jx] : cplx<R>{0, 0};
+  if (ec.h2) {
+    // entropy step: the range-spectra cotangent is alpha h1 + (beta + alpha cc[col block]) h2
+    double S, T;
+    if (ec.partials) {
+      double es = 0.0, et = 0.0;
+      for (int i = threadIdx.x; i < ec.nparts; i += NT) {
+        es += ec.partials[2 * i];
+        et += ec.partials[2 * i + 1];
+      }
+      S = block_sum<NT>(es);
+      T = block_sum<NT>(et);
+      if (ec.loss && n == 0 && threadIdx.x == 0) *ec.loss = S > 0.0 ? log(S) - T / S : 0.0;
+    } else {
+      S = ec.stats[0];
+      T = S > 0.0 ? S * (log(S) - ec.stats[1]) : 0.0;
+    }
+    const double al = S > 0.0 ? -2.0 / S : 0.0, be = S > 0.0 ? 2.0 * T / (S * S) : 0.0;
+    const cplx<R>* in2 = ec.h2 + (size_t)n * mx;
+    for (int i = threadIdx.x; i < N; i += NT) {
+      const int jp = i < N / 2 ? i : i - N;
+      const int jx = jp + mx / 2;
+      cplx<R> v = {0, 0};
+      if (jx >= 0 && jx < mx) {
+        const R c2 = (R)(be + al * (double)ec.cblk[jx / ec.cb]);
+        v = t.deapx[jx] * ((R)al * in[jx] + c2 * in2[jx]);
+      }
+      buf[i] = v;
+    }
+  } else {
+    for (int i = threadIdx.x; i < N; i += NT) {
+      const int jp = i < N / 2 ? i : i - N;
+      const int jx = jp + mx / 2;
+      buf[i] = (jx >= 0 && jx < mx) ? t.deapx[jx] * in[jx] : cplx<R>{0, 0};
+    }
   }
   const cplx<R> rot = row_rotation(t, phase, dalong, n);
   const double ku = t.ku[n];
@@ -1007,6 +1328,21 @@ constexpr int nt_for() {
   return LOGN <= 8 ? 64 : (LOGN <= 11 ? 256 : (LOGN == 12 ? 256 : (LOGN == 13 ? 512 : 1024)));
 }
 
+int rows_threads(int logn) {
+  switch (logn) {
+    case 6: return nt_for<6>();
+    case 7: return nt_for<7>();
+    case 8: return nt_for<8>();
+    case 9: return nt_for<9>();
+    case 10: return nt_for<10>();
+    case 11: return nt_for<11>();
+    case 12: return nt_for<12>();
+    case 13: return nt_for<13>();
+    case 14: return nt_for<14>();
+  }
+  return 0;
+}
+
 static hipError_t allow_lds(const void* fn, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -1053,9 +1389,13 @@ hipError_t launch_fwd_rows(const Geo& g, const Tab<R>& t, int stype, const void*
                            const R* dalong, const R* w, cplx<R>* out, int stage, hipStream_t st) {
   const size_t lds = sizeof(cplx<R>) * (((size_t)1 << g.lognfx) + ((size_t)1 << g.lognfx) / 64 + 64) +
                      sizeof(float) * kPolyLds;
+  if (g.range_mode == 1 && g.W > kRunWindow) return hipErrorInvalidValue;
   TFFR_LOGN_DISPATCH(g.lognfx, {
     constexpr int NT = nt_for<L>();
-    auto fn = g.sub <= 4 ? k_fwd_rows<R, L, NT, 4> : (g.sub <= 8 ? k_fwd_rows<R, L, NT, 8> : k_fwd_rows<R, L, NT, 16>);
+    auto fn = g.range_mode == 1
+                  ? k_fwd_rows_run<R, L, NT, kRunWindow>
+                  : (g.sub <= 4 ? k_fwd_rows<R, L, NT, 4>
+                                : (g.sub <= 8 ? k_fwd_rows<R, L, NT, 8> : k_fwd_rows<R, L, NT, 16>));
     hipError_t e = allow_lds((const void*)fn, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fn, dim3(g.n_pulses), dim3(NT), lds, st, g, t, stype, samples, phase, dalong, w, out, stage);
@@ -1117,9 +1457,27 @@ hipError_t launch_adj_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>*
 }
 
 template <typename R>
+hipError_t launch_ent_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>* hx, cplx<R>* img, double* partials,
+                           R* cblk, cplx<R>* h1, cplx<R>* h2, hipStream_t st) {
+  const size_t nfy = (size_t)1 << g.lognfy;
+  const size_t lds = sizeof(cplx<R>) * (nfy * cb + std::max<size_t>((size_t)g.n_pulses * cb, nfy * cb) + nfy / 64 + 64);
+  const int grid = (g.mx + cb - 1) / cb;
+  TFFR_LOGN_DISPATCH(g.lognfy, {
+    TFFR_CB_DISPATCH(cb, {
+      constexpr int NT = nt_cols<L, CB>();
+      auto fn = k_ent_cols<R, L, NT, CB>;
+      hipError_t e = allow_lds((const void*)fn, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), lds, st, g, t, hx, img, partials, cblk, h1, h2);
+      return hipGetLastError();
+    })
+  })
+}
+
+template <typename R>
 hipError_t launch_adj_rows(const Geo& g, const Tab<R>& t, int stype, const cplx<R>* hx, const void* samples,
                            const R* phase, const R* dalong, const R* w, cplx<R>* grad_s, R* grad_phase,
-                           R* grad_dalong, hipStream_t st) {
+                           R* grad_dalong, const EntComb<R>& ec, hipStream_t st) {
   size_t lds = sizeof(cplx<R>) * (((size_t)1 << g.lognfx) + ((size_t)1 << g.lognfx) / 64 + 64) +
                sizeof(float) * kPolyLds;
   if (g.weighting == 2) lds += sizeof(cplx<R>) * (size_t)g.n_freq;
@@ -1129,7 +1487,7 @@ hipError_t launch_adj_rows(const Geo& g, const Tab<R>& t, int stype, const cplx<
     hipError_t e = allow_lds((const void*)fn, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fn, dim3(g.n_pulses), dim3(NT), lds, st, g, t, stype, hx, samples, phase, dalong, w,
-                       grad_s, grad_phase, grad_dalong);
+                       grad_s, grad_phase, grad_dalong, ec);
     return hipGetLastError();
   })
 }
@@ -1232,8 +1590,10 @@ hipError_t launch_fft(int log2n, int batch, int sign, const cplx<R>* in, cplx<R>
                                          hipStream_t);                                                         \
   template hipError_t launch_adj_cols<R>(const Geo&, const Tab<R>&, int, const cplx<R>*, cplx<R>*, const double*, \
                                          const double*, int, double*, hipStream_t);                             \
+  template hipError_t launch_ent_cols<R>(const Geo&, const Tab<R>&, int, const cplx<R>*, cplx<R>*, double*, R*,   \
+                                         cplx<R>*, cplx<R>*, hipStream_t);                                     \
   template hipError_t launch_adj_rows<R>(const Geo&, const Tab<R>&, int, const cplx<R>*, const void*, const R*, \
-                                         const R*, const R*, cplx<R>*, R*, R*, hipStream_t);                   \
+                                         const R*, const R*, cplx<R>*, R*, R*, const EntComb<R>&, hipStream_t); \
   template hipError_t launch_weights<R>(const Geo&, const Tab<R>&, R*, unsigned long long*, int, hipStream_t);  \
   template hipError_t launch_ffr<R>(const Geo&, const Tab<R>&, double*, R*, int*, hipStream_t);                \
   template hipError_t launch_entropy<R>(const Geo&, const cplx<R>*, double*, int, double*, cplx<R>*,          \

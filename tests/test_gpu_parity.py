@@ -68,6 +68,47 @@ def test_range_gridding_stage(weighting):
     assert rel_l2(got, ref) < 2e-6
 
 
+# Dense slices (consecutive samples ~0.3-1.3 fine cells apart at fov 40 m) go to the
+# sliding-window range kernel, sparse ones to the sub-pass kernel; TFFR_RANGE_MODE forces
+# either at plan creation.  Rows wider than the fine row are cut into several parts.
+DENSE = [(6, 256, 32), (4, 1000, 64), (3, 777, 128)]
+
+
+@pytest.mark.parametrize("mode", ["0", "1"])
+@pytest.mark.parametrize("size", DENSE)
+def test_range_gridding_modes_dense(size, mode, monkeypatch):
+    print(f"gridding stage, dense rows size={size} range mode={mode}", flush=True)
+    monkeypatch.setenv("TFFR_RANGE_MODE", mode)
+    case = Case(*size, weighting=T.W_TFFR, seed=5)
+    s, st = case.samples()
+    phase = case.rng.normal(0, 0.5, size[0])
+    got = case.plan.tffr_debug_rows(st, stage=0, phase=case.real(phase)).cpu().numpy()
+    c = OP.weighted_samples(case.prob, s, case.rounded(phase))
+    ref = es_spread_rows_cpu(case, c)
+    assert rel_l2(got, ref) < 2e-6
+
+
+@pytest.mark.parametrize("mode", ["0", "1"])
+@pytest.mark.parametrize("weighting,dtype,n_freq", [(T.W_TFFR, T.C64, 600), (T.W_QUAD, T.C64, 600),
+                                                    (T.W_TFFR, T.C128, 600), (T.W_TFFR, T.C64_FP16IN, 600),
+                                                    (T.W_FFR, T.C64, 145)])
+def test_forward_dense_rows_both_range_modes(weighting, dtype, n_freq, mode, monkeypatch):
+    print(f"forward, dense rows, weighting={weighting} dtype={dtype} n_freq={n_freq} range mode={mode}",
+          flush=True)
+    monkeypatch.setenv("TFFR_RANGE_MODE", mode)
+    # plain FFR needs a full-rank frame product: ~1.1 lattice units (2.2 fine cells) apart
+    case = Case(5, n_freq, 64, weighting=weighting, dtype=dtype, width=7, seed=13)
+    s, st = case.samples()
+    phase = case.rng.normal(0, 0.5, 5)
+    dal = case.rng.normal(0, 0.004, 5)
+    got = case.plan.tffr_forward(st, case.real(phase), case.real(dal)).cpu().numpy()
+    ref = OP.image(case.prob, s, case.rounded(phase), case.rounded(dal))
+    err = rel_l2(got, ref)
+    print(f"  rel-L2 {err:.3e}", flush=True)
+    # width 7 in complex128 is limited by the kernel (~1e-6), not by the arithmetic
+    assert err < 1e-5
+
+
 # ---------------------------------------------------------------- weights
 @pytest.mark.parametrize("tau,mode", [(0.97, OW.THRESH_LITERAL), (1.03, OW.THRESH_LITERAL),
                                       (0.97, OW.THRESH_CORRELATION), (0.9, OW.THRESH_CORRELATION)])
