@@ -51,8 +51,8 @@ typedef enum {
   TFFR_OK = 0,
   TFFR_ERR_ARG = 1,          /* bad size, pointer or parameter value               */
   TFFR_ERR_EVANESCENT = 2,   /* some sample has 4 k^2 <= ku^2                       */
-  TFFR_ERR_NONMONOTONE = 3,  /* k is not strictly increasing                        */
-  TFFR_ERR_LAYOUT = 4,       /* buffer too small / misaligned                       */
+  TFFR_ERR_NONMONOTONE = 3,  /* k (or kx along a slice) is not strictly increasing  */
+  TFFR_ERR_LAYOUT = 4,       /* buffer misaligned, or ky not constant along a slice  */
   TFFR_ERR_UNSUPPORTED = 5,  /* width, dtype, grid size or FFR band not supported   */
   TFFR_ERR_SINGULAR = 6,     /* plain-FFR frame product has a vanishing pivot       */
   TFFR_ERR_NOMEM = 7,        /* device or host allocation of plan tables failed     */
@@ -106,10 +106,24 @@ tffr_status tffr_validate(const tffr_params *p, const double *k, const double *k
 tffr_status tffr_plan_create(const tffr_params *p, const double *k, const double *ku,
                              tffr_plan **out);
 
+/* Plans from explicit sample coordinates instead of the Stolt map: any geometry with
+ * the slice structure the method relies on (Sec. II-A: each slice has one ky, its
+ * samples are non-uniform in kx only; Algorithm 1 loops over such slices).
+ *   kx, ky: host [n_pulses][n_freq] rad/m, copied (the plan keeps kx on the device,
+ *           8 bytes per sample).  Along every slice n, ky[n][p] must be one value
+ *           (else TFFR_ERR_LAYOUT) and kx[n][p] strictly increasing in p (else
+ *           TFFR_ERR_NONMONOTONE); non-finite values give TFFR_ERR_ARG.
+ * The plan then behaves as one from tffr_plan_create with kx, ky in place of the
+ * Stolt map (dalong scales with that ky).  tffr_validate_xy is the host-only check. */
+tffr_status tffr_validate_xy(const tffr_params *p, const double *kx, const double *ky);
+tffr_status tffr_plan_create_xy(const tffr_params *p, const double *kx, const double *ky,
+                                tffr_plan **out);
+
 void tffr_plan_destroy(tffr_plan *plan);
 
 /* Bytes of caller-owned device workspace every forward / adjoint / entropy / weights
- * call needs (the per-slice range spectra plus reduction scratch).  0 for NULL. */
+ * call needs (two [n_pulses][mx] complex arrays of per-slice range spectra plus
+ * reduction scratch).  0 for NULL. */
 size_t tffr_workspace_bytes(const tffr_plan *plan);
 
 /* Sizes chosen by the plan: fine grid in range and azimuth, ES kernel shape beta,
@@ -164,8 +178,11 @@ tffr_status tffr_entropy(tffr_plan *plan, const void *d_image, double *d_loss,
 
 /* One autofocus-style step, fused: forward image, image entropy E (as tffr_entropy),
  * and the adjoint of dE/dI (as tffr_adjoint with grad_image = tffr_entropy's gradient)
- * without materialising dE/dI: the azimuth forward kernel also reduces the entropy sums
- * and the first adjoint kernel forms the gradient from the image in registers.
+ * without materialising dE/dI.  The gradient is alpha I (ln|I|^2 - c) + (beta + alpha c) I
+ * with alpha, beta fixed by the global sums of |I|^2 and |I|^2 ln|I|^2, so one azimuth
+ * kernel forms each image column, its share of the sums and the adjoint azimuth
+ * transforms of both fields; the range adjoint combines them.  Three kernel launches
+ * (four when the image has more than 1024 column blocks).
  *   arguments as in tffr_forward / tffr_adjoint; d_image is written (range-major) and
  *   d_loss (device double[1]) receives E; d_samples is required; d_grad_phase and
  *   d_grad_dalong may be NULL. */
@@ -173,6 +190,17 @@ tffr_status tffr_entropy_step(tffr_plan *plan, const void *d_samples, const void
                               const void *d_dalong, const void *d_user_w, void *d_image,
                               double *d_loss, void *d_grad_samples, void *d_grad_phase,
                               void *d_grad_dalong, void *d_work, tffr_stream stream);
+
+/* Per-slice phase and position gradients from a sample cotangent computed elsewhere:
+ *   d_samples      [n_pulses][n_freq] complex (dtype), the raw samples s
+ *   d_grad_samples [n_pulses][n_freq] complex (real type of the plan): dL/dRe s + i dL/dIm s
+ *   d_grad_phase   [n_pulses] real, written: dL/dphi_n = sum_p (Im g_np Re s_np - Re g_np Im s_np)
+ *   d_grad_dalong  [n_pulses] real or NULL, written: ky_n dL/dphi_n
+ * This is the reduction tffr_adjoint performs when its gradient outputs are non-NULL
+ * (the row phase exp(i(phi_n + ky_n du_n)) multiplies every sample of slice n, so
+ * dL/dphi_n = sum_p Re(conj(dL/ds') i s') = sum_p Re(conj(g) i s)); FP64 accumulation. */
+tffr_status tffr_row_phase_grad(tffr_plan *plan, const void *d_samples, const void *d_grad_samples,
+                                void *d_grad_phase, void *d_grad_dalong, tffr_stream stream);
 
 const char *tffr_status_string(tffr_status s);
 

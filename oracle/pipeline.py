@@ -46,9 +46,17 @@ class Problem:
     r: int = 2  # FFR band
     tau: float = 0.97  # tFFR threshold
     thresh_mode: int = weights.THRESH_LITERAL
+    # explicit sample coordinates instead of the Stolt map of (k, ku): kx [n_pulses][n_freq],
+    # ky [n_pulses] (each slice keeps one ky, as the slice structure of Algorithm 1 needs)
+    kx_explicit: np.ndarray = None
+    ky_explicit: np.ndarray = None
 
     def geometry(self):
-        kx, ky = geometry.stolt(self.k, self.ku)
+        if self.kx_explicit is not None:
+            kx = np.asarray(self.kx_explicit, dtype=np.float64)
+            ky = np.asarray(self.ky_explicit, dtype=np.float64)
+        else:
+            kx, ky = geometry.stolt(self.k, self.ku)
         lam = geometry.lattice_coordinate(kx, self.fov_x)
         X = geometry.pixel_coordinates(self.mx, self.fov_x)
         Y = geometry.pixel_coordinates(self.my, self.fov_y)

@@ -45,6 +45,8 @@ _PROTOS = {
     "tffr_default_params": (None, [ctypes.POINTER(Params)]),
     "tffr_validate": (ctypes.c_int, [ctypes.POINTER(Params), _dp, _dp]),
     "tffr_plan_create": (ctypes.c_int, [ctypes.POINTER(Params), _dp, _dp, ctypes.POINTER(_vp)]),
+    "tffr_validate_xy": (ctypes.c_int, [ctypes.POINTER(Params), _dp, _dp]),
+    "tffr_plan_create_xy": (ctypes.c_int, [ctypes.POINTER(Params), _dp, _dp, ctypes.POINTER(_vp)]),
     "tffr_plan_destroy": (None, [_vp]),
     "tffr_workspace_bytes": (ctypes.c_size_t, [_vp]),
     "tffr_plan_info": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -55,6 +57,7 @@ _PROTOS = {
     "tffr_adjoint": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tffr_entropy": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "tffr_entropy_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "tffr_row_phase_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "tffr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "tffr_debug_fft": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]),
     "tffr_debug_rows": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]),

@@ -138,7 +138,7 @@ struct tffr_plan {
   int ffr_halfband = 0;
   double beta = 0.0;
   // device tables
-  DevBuf k, ku, ky, ystart, ytap, deapx, deapy, twx, twy, poly, ffr_d, ycn, ycw;
+  DevBuf k, ku, kx, ky, ystart, ytap, deapx, deapy, twx, twy, poly, ffr_d, ycn, ycw;
   // workspace layout
   bool ent_fused = false;  // entropy step uses the fused azimuth kernel
   size_t off_hx = 0, off_h2 = 0, off_cblk = 0, off_part = 0, off_stats = 0, off_kept = 0, off_count = 0, off_status = 0, off_gband = 0, off_zband = 0,
@@ -169,6 +169,7 @@ tffr::Tab<R> tables(const tffr_plan* P) {
   tffr::Tab<R> t;
   t.k = (const double*)P->k.p;
   t.ku = (const double*)P->ku.p;
+  t.kx = (const double*)P->kx.p;
   t.ky = (const R*)P->ky.p;
   t.ystart = (const int32_t*)P->ystart.p;
   t.ytap = (const R*)P->ytap.p;
@@ -232,6 +233,18 @@ bool fit_weight_poly(double a, double q, int nseg, int deg, std::vector<float>& 
   return true;
 }
 
+// Range wavenumber of sample (n, i) on the host: the Stolt map of (k, ku), or the
+// explicit table of a plan made from coordinates.  Same operation order as the kernels.
+struct HostKx {
+  const double* k;
+  const double* ku;
+  const double* kx;
+  int n_freq;
+  double operator()(int n, int i) const {
+    return kx ? kx[(size_t)n * n_freq + i] : std::sqrt(4.0 * (k[i] * k[i]) - ku[n] * ku[n]);
+  }
+};
+
 tffr_status check_params(const tffr_params* p) {
   if (!p) return TFFR_ERR_ARG;
   if (p->n_pulses < 1 || p->n_freq < 1) return TFFR_ERR_ARG;
@@ -255,11 +268,11 @@ tffr_status check_params(const tffr_params* p) {
 
 // Half bandwidth of the frame product: the largest |p - p'| whose windows
 // (lam - q, lam + q) share an integer, over all slices (plus one for rounding).
-int ffr_halfband(const tffr_params* p, const double* k, const double* ku) {
+int ffr_halfband(const tffr_params* p, const HostKx& kx) {
   int b = 0;
   std::vector<double> lam(p->n_freq);
   for (int n = 0; n < p->n_pulses; ++n) {
-    for (int i = 0; i < p->n_freq; ++i) lam[i] = std::sqrt(4.0 * (k[i] * k[i]) - ku[n] * ku[n]) * p->fov_x / (2.0 * kPi);
+    for (int i = 0; i < p->n_freq; ++i) lam[i] = kx(n, i) * p->fov_x / (2.0 * kPi);
     int j = 0;
     for (int i = 0; i < p->n_freq; ++i) {
       const double top = std::ceil(lam[i] + p->q) - 1.0;  // largest integer < lam + q
@@ -367,15 +380,14 @@ bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 // under kDenseSpacing cells apart; each of its threads takes at most one run per part.
 constexpr double kDenseSpacing = 2.5;
 
-void range_schedule(const tffr_params* p, const double* k, const double* ku, int nfx, int nt, int* S, int* part_len,
-                    int* mode) {
+void range_schedule(const tffr_params* p, const HostKx& kx, int nfx, int nt, int* S, int* part_len, int* mode) {
   const double tx = p->fov_x / (2.0 * kPi * p->mx);
   const int P = p->n_freq, W = p->kernel_width;
   double smin = 1e300, smax = 0.0;
   int Q = 1;
   std::vector<double> U(P);
   for (int n = 0; n < p->n_pulses; ++n) {
-    for (int i = 0; i < P; ++i) U[i] = std::sqrt(4.0 * (k[i] * k[i]) - ku[n] * ku[n]) * tx * nfx;
+    for (int i = 0; i < P; ++i) U[i] = kx(n, i) * tx * nfx;
     for (int i = 0; i + 1 < P; ++i) {
       smin = std::min(smin, U[i + 1] - U[i]);
       smax = std::max(smax, U[i + 1] - U[i]);
@@ -455,15 +467,40 @@ tffr_status tffr_validate(const tffr_params* p, const double* k, const double* k
   for (int i = 0; i < p->n_freq; ++i) kmin = std::min(kmin, std::fabs(k[i]));
   for (int i = 0; i < p->n_pulses; ++i) kumax = std::max(kumax, std::fabs(ku[i]));
   if (!(4.0 * (kmin * kmin) - kumax * kumax > 0.0)) return TFFR_ERR_EVANESCENT;
-  if (p->weighting == TFFR_W_FFR && ffr_halfband(p, k, ku) > kMaxHalfBand) return TFFR_ERR_UNSUPPORTED;
+  if (p->weighting == TFFR_W_FFR && ffr_halfband(p, HostKx{k, ku, nullptr, p->n_freq}) > kMaxHalfBand)
+    return TFFR_ERR_UNSUPPORTED;
   return TFFR_OK;
 }
 
-tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double* ku, tffr_plan** out) {
-  if (!out) return TFFR_ERR_ARG;
-  *out = nullptr;
-  tffr_status s = tffr_validate(p, k, ku);
+tffr_status tffr_validate_xy(const tffr_params* p, const double* kx, const double* ky) {
+  tffr_status s = check_params(p);
   if (s != TFFR_OK) return s;
+  if (!kx || !ky) return TFFR_ERR_ARG;
+  const size_t nf = (size_t)p->n_freq;
+  for (size_t i = 0; i < (size_t)p->n_pulses * nf; ++i)
+    if (!std::isfinite(kx[i]) || !std::isfinite(ky[i])) return TFFR_ERR_ARG;
+  for (int n = 0; n < p->n_pulses; ++n) {
+    const double* r = kx + n * nf;
+    const double* y = ky + n * nf;
+    for (size_t i = 1; i < nf; ++i) {
+      if (y[i] != y[0]) return TFFR_ERR_LAYOUT;
+      if (!(r[i] > r[i - 1])) return TFFR_ERR_NONMONOTONE;
+    }
+  }
+  if (p->weighting == TFFR_W_FFR && ffr_halfband(p, HostKx{nullptr, nullptr, kx, p->n_freq}) > kMaxHalfBand)
+    return TFFR_ERR_UNSUPPORTED;
+  return TFFR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Plan from (k, ku) (Stolt map in the kernels) or from explicit coordinates (kx_tab
+// non-null; ku then holds each slice's ky).
+tffr_status plan_create(const tffr_params* p, const double* k, const double* ku, const double* kx_tab,
+                        tffr_plan** out) {
+  tffr_status s = TFFR_OK;
   tffr_plan* P = new (std::nothrow) tffr_plan();
   if (!P) return TFFR_ERR_NOMEM;
   P->prm = *p;
@@ -532,7 +569,11 @@ tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double
   g.near_f = (float)g.near_rel;
   g.thr_f = (float)(p->thresh_mode == TFFR_THRESH_LITERAL ? p->tau : 1.0 / p->tau);
 
-  std::vector<double> kv(k, k + p->n_freq), kuv(ku, ku + p->n_pulses);
+  std::vector<double> kv, kuv(ku, ku + p->n_pulses), kxv;
+  if (kx_tab)
+    kxv.assign(kx_tab, kx_tab + (size_t)p->n_pulses * p->n_freq);
+  else
+    kv.assign(k, k + p->n_freq);
   // per-slice azimuth taps
   std::vector<int32_t> ys(p->n_pulses);
   std::vector<double> taps((size_t)p->n_pulses * W);
@@ -561,7 +602,8 @@ tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double
       cw[slot] = taps[(size_t)n * W + i];
     }
   g.yemax = yemax;
-  range_schedule(p, k, ku, nfx, tffr::rows_threads(lognx), &g.sub, &g.part_len, &g.range_mode);
+  const HostKx hkx{k, ku, kx_tab, p->n_freq};
+  range_schedule(p, hkx, nfx, tffr::rows_threads(lognx), &g.sub, &g.part_len, &g.range_mode);
   std::vector<double> dx = deapod_table(p->mx, nfx, W, P->beta), dy = deapod_table(p->my, nfy, W, P->beta);
   std::vector<double> twx = twiddle_table(nfx), twy = twiddle_table(nfy);
   if (P->dbl()) {
@@ -582,6 +624,7 @@ tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double
     if (s == TFFR_OK) s = upload(P->twy, cast<float>(twy));
   }
   if (s == TFFR_OK) s = upload(P->k, kv);
+  if (s == TFFR_OK) s = upload(P->kx, kxv);
   if (s == TFFR_OK) s = upload(P->ku, kuv);
   if (s == TFFR_OK) s = upload(P->ystart, ys);
   if (s == TFFR_OK) s = upload(P->ycn, cn);
@@ -619,7 +662,7 @@ tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double
   P->off_status = off;
   off = align_up(off + sizeof(int));
   if (p->weighting == TFFR_W_FFR) {
-    P->ffr_halfband = ffr_halfband(p, k, ku);
+    P->ffr_halfband = ffr_halfband(p, hkx);
     g.band_b = P->ffr_halfband;
     if ((size_t)p->n_freq * (2 * g.band_b + 1) * sizeof(double) > lds_max) return fail(TFFR_ERR_UNSUPPORTED);
     const size_t N = (size_t)p->n_pulses * p->n_freq;
@@ -654,6 +697,28 @@ tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double
   if (hipDeviceSynchronize() != hipSuccess) return fail(TFFR_ERR_HIP);
   *out = P;
   return TFFR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tffr_status tffr_plan_create(const tffr_params* p, const double* k, const double* ku, tffr_plan** out) {
+  if (!out) return TFFR_ERR_ARG;
+  *out = nullptr;
+  const tffr_status s = tffr_validate(p, k, ku);
+  if (s != TFFR_OK) return s;
+  return plan_create(p, k, ku, nullptr, out);
+}
+
+tffr_status tffr_plan_create_xy(const tffr_params* p, const double* kx, const double* ky, tffr_plan** out) {
+  if (!out) return TFFR_ERR_ARG;
+  *out = nullptr;
+  const tffr_status s = tffr_validate_xy(p, kx, ky);
+  if (s != TFFR_OK) return s;
+  std::vector<double> ky_row(p->n_pulses);
+  for (int n = 0; n < p->n_pulses; ++n) ky_row[n] = ky[(size_t)n * p->n_freq];
+  return plan_create(p, nullptr, ky_row.data(), kx, out);
 }
 
 void tffr_plan_destroy(tffr_plan* plan) { delete plan; }
@@ -712,6 +777,21 @@ tffr_status tffr_entropy_step(tffr_plan* P, const void* smp, const void* ph, con
   hipStream_t st = (hipStream_t)stream;
   return P->dbl() ? do_entropy_step<double>(P, smp, ph, da, uw, img, loss, gs, gph, gda, work, st)
                   : do_entropy_step<float>(P, smp, ph, da, uw, img, loss, gs, gph, gda, work, st);
+}
+
+tffr_status tffr_row_phase_grad(tffr_plan* P, const void* smp, const void* gs, void* gph, void* gda,
+                                tffr_stream stream) {
+  if (!P || !smp || !gs || !gph) return TFFR_ERR_ARG;
+  if (!aligned(gs, P->csize() / 2) || !aligned(smp, 4) || !aligned(gph, P->rsize()) ||
+      (gda && !aligned(gda, P->rsize())))
+    return TFFR_ERR_LAYOUT;
+  hipStream_t st = (hipStream_t)stream;
+  const hipError_t e =
+      P->dbl() ? tffr::launch_row_phase_grad<double>(P->geo, tables<double>(P), sample_type(P), smp,
+                                                     (const cplx<double>*)gs, (double*)gph, (double*)gda, st)
+               : tffr::launch_row_phase_grad<float>(P->geo, tables<float>(P), sample_type(P), smp,
+                                                    (const cplx<float>*)gs, (float*)gph, (float*)gda, st);
+  return hip_status(e);
 }
 
 tffr_status tffr_weights(tffr_plan* P, void* d_w, void* work, tffr_stream stream) {

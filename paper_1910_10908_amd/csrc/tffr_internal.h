@@ -44,7 +44,8 @@ struct Geo {
 template <typename R>
 struct Tab {
   const double* k;        // [n_freq]   fast-time wavenumbers
-  const double* ku;       // [n_pulses] azimuth wavenumbers
+  const double* ku;       // [n_pulses] azimuth wavenumbers (= ky of the slice)
+  const double* kx;       // [n_pulses][n_freq] explicit range wavenumbers, or null: Stolt map of k, ku
   const R* ky;            // [n_pulses] ky = ku in the compute type (row phase)
   const int32_t* ystart;  // [n_pulses] first azimuth fine cell of the slice's taps
   const R* ytap;          // [n_pulses][W] azimuth kernel taps of the slice
@@ -95,6 +96,9 @@ hipError_t launch_adj_rows(const Geo& g, const Tab<R>& t, int stype, const cplx<
                            const void* samples, const R* phase, const R* dalong, const R* w,
                            cplx<R>* grad_s, R* grad_phase, R* grad_dalong, const EntComb<R>& ec,
                            hipStream_t st);
+template <typename R>
+hipError_t launch_row_phase_grad(const Geo& g, const Tab<R>& t, int stype, const void* samples,
+                                 const cplx<R>* grad_s, R* grad_phase, R* grad_dalong, hipStream_t st);
 template <typename R>
 hipError_t launch_weights(const Geo& g, const Tab<R>& t, R* w, unsigned long long* kept_partial,
                           int nblocks, hipStream_t st);

@@ -220,6 +220,16 @@ __device__ __forceinline__ double stolt_kx(double k, double ku) {
 __device__ __forceinline__ double lattice_coord(double kx, const Geo& g) {
   return (kx * g.tx_scale) * (double)g.mx;
 }
+// Range wavenumber of sample (n, p) in two steps, so the load can be issued early: the
+// raw value (k[p], or the explicit kx[n][p] of a plan made from coordinates), then kx.
+template <typename R>
+__device__ __forceinline__ double raw_k(const Tab<R>& t, int n_freq, int n, int p) {
+  return t.kx ? t.kx[(size_t)n * n_freq + p] : t.k[p];
+}
+template <typename R>
+__device__ __forceinline__ double kx_of(const Tab<R>& t, double raw, double ku) {
+  return t.kx ? raw : stolt_kx(raw, ku);
+}
 
 // Finite-interval cosine transforms of w = exp(-a|t|) and 1/w over [-1/2, 1/2]
 // (the entries of W and Psi on the image's own lattice); ema2 = exp(-a/2), epa2 = exp(a/2).
@@ -301,7 +311,7 @@ constexpr int kPolyLds = 512;  // floats reserved in LDS for the weight polynomi
 
 // Weight of sample (n, p) for the diagonal methods.
 template <typename R>
-__device__ __forceinline__ R diag_weight(const Geo& g, const Tab<R>& t, const float* poly, double ku, int p,
+__device__ __forceinline__ R diag_weight(const Geo& g, const Tab<R>& t, const float* poly, double ku, int n, int p,
                                          double lam) {
   switch (g.weighting) {
     case 3:  // tFFR
@@ -309,8 +319,8 @@ __device__ __forceinline__ R diag_weight(const Geo& g, const Tab<R>& t, const fl
     case 1: {  // trapezoid quadrature in lam along the slice
       if (g.n_freq == 1) return (R)1;
       const int plo = p > 0 ? p - 1 : 0, phi = p < g.n_freq - 1 ? p + 1 : g.n_freq - 1;
-      const double llo = lattice_coord(stolt_kx(t.k[plo], ku), g);
-      const double lhi = lattice_coord(stolt_kx(t.k[phi], ku), g);
+      const double llo = lattice_coord(kx_of(t, raw_k(t, g.n_freq, n, plo), ku), g);
+      const double lhi = lattice_coord(kx_of(t, raw_k(t, g.n_freq, n, phi), ku), g);
       return (R)((lhi - llo) / 2.0);
     }
     default:
@@ -392,7 +402,7 @@ __device__ __forceinline__ cplx<R> weighted_sample(const Geo& g, const Tab<R>& t
   const size_t base = (size_t)n * g.n_freq;
   if (g.weighting == 2)  // plain FFR: banded D within the slice
     return cmul(rot, ffr_apply<R>(samples, stype, w, base, p, g.n_freq, g.band_r));
-  const R wt = w ? w[base + p] : diag_weight<R>(g, t, poly, ku, p, lam);
+  const R wt = w ? w[base + p] : diag_weight<R>(g, t, poly, ku, n, p, lam);
   return wt * cmul(rot, s);
 }
 
@@ -442,7 +452,7 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(Geo g, Tab<R> t, int stype, con
         for (int j = 0; j < SG; ++j) {
           const int p = p0 + j0 + j;
           const bool ok = j0 + j < S && p < pb;
-          kr[j] = ok ? t.k[p] : 0.0;
+          kr[j] = ok ? raw_k(t, g.n_freq, n, p) : 0.0;
           sr[j] = (ok && !ffr) ? load_sample<R>(samples, stype, base + p) : cplx<R>{0, 0};
         }
         if (first) {
@@ -454,7 +464,7 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(Geo g, Tab<R> t, int stype, con
           if (j0 + j < S) {
             const int p = p0 + j0 + j;
             if (p < pb) {
-              const double kx = stolt_kx(kr[j], ku);
+              const double kx = kx_of(t, kr[j], ku);
               const double lam = lattice_coord(kx, g);
               const cplx<R> c = weighted_sample<R>(g, t, poly, stype, samples, w, n, p, ku, lam, rot, sr[j]);
               int ui;
@@ -551,16 +561,16 @@ __global__ __launch_bounds__(NT) void k_fwd_rows_run(Geo g, Tab<R> t, int stype,
       acc[WM - 1] = cplx<R>{0, 0};
       ++base;
     };
-    double k_nx = p0 < p1 ? t.k[p0] : 0.0;
+    double k_nx = p0 < p1 ? raw_k(t, g.n_freq, n, p0) : 0.0;
     cplx<R> s_nx = (p0 < p1 && !ffr) ? load_sample<R>(samples, stype, base_s + p0) : cplx<R>{0, 0};
     for (int p = p0; p < p1; ++p) {
       const double kp = k_nx;
       const cplx<R> sp = s_nx;
       if (p + 1 < p1) {
-        k_nx = t.k[p + 1];
+        k_nx = raw_k(t, g.n_freq, n, p + 1);
         if (!ffr) s_nx = load_sample<R>(samples, stype, base_s + p + 1);
       }
-      const double kx = stolt_kx(kp, ku);
+      const double kx = kx_of(t, kp, ku);
       const double lam = lattice_coord(kx, g);
       const cplx<R> c = weighted_sample<R>(g, t, poly, stype, samples, w, n, p, ku, lam, rot, sp);
       const double tt = kx * g.tx_scale;
@@ -569,7 +579,7 @@ __global__ __launch_bounds__(NT) void k_fwd_rows_run(Geo g, Tab<R> t, int stype,
       fine_pos<R>(tt, N, ui, f);
       const int k0 = (int)ceil(f - halfw);
       // unwrapped first tap cell (only differences and the low LOGN bits are used)
-      const int c0 = (int)((unsigned)floor(tt) * (unsigned)N + (unsigned)(ui + k0));
+      const int c0 = (int)((unsigned)(int)floor(tt) * (unsigned)N + (unsigned)(ui + k0));
       if (p == p0) base = cfirst = c0;
       for (int adv = c0 - base; adv > 0; --adv) retire();
       const R z0 = ((R)k0 - f) * inv_halfw;
@@ -954,7 +964,7 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
   const bool want_phase = grad_phase || grad_dalong;
   const bool need_s = want_phase && !ffr;
   int p_next = threadIdx.x;
-  double k_next = p_next < g.n_freq ? t.k[p_next] : 0.0;
+  double k_next = p_next < g.n_freq ? raw_k(t, g.n_freq, n, p_next) : 0.0;
   cplx<R> s_next = (need_s && p_next < g.n_freq) ? load_sample<R>(samples, stype, base + p_next) : cplx<R>{0, 0};
   R w_next = (w && !ffr && p_next < g.n_freq) ? w[base + p_next] : (R)0;
   load_twiddles<N, NT>(tw, t.twx);
@@ -1007,11 +1017,11 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
     const R wp = w_next;
     p_next = p + NT;
     if (p_next < g.n_freq) {
-      k_next = t.k[p_next];
+      k_next = raw_k(t, g.n_freq, n, p_next);
       if (need_s) s_next = load_sample<R>(samples, stype, base + p_next);
       if (w && !ffr) w_next = w[base + p_next];
     }
-    const double kx = stolt_kx(kp, ku);
+    const double kx = kx_of(t, kp, ku);
     int ui;
     R f;
     fine_pos<R>(kx * g.tx_scale, N, ui, f);
@@ -1027,7 +1037,7 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
       gbuf[p] = a;
       continue;
     }
-    const R wt = w ? wp : diag_weight<R>(g, t, poly, ku, p, lattice_coord(kx, g));
+    const R wt = w ? wp : diag_weight<R>(g, t, poly, ku, n, p, lattice_coord(kx, g));
     const cplx<R> gs = cmulc(wt * a, rot);  // exp(-i psi) D^T A^H
     grad_s[base + p] = gs;
     if (want_phase) acc_phase += (double)gs.y * (double)sp.x - (double)gs.x * (double)sp.y;
@@ -1058,6 +1068,28 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
   }
 }
 
+// Per-slice phase and position gradients from a sample cotangent g (w.r.t. the raw
+// samples s): dL/dphi_n = sum_p Re(conj(g) i s) = sum_p (Im g Re s - Re g Im s), FP64
+// accumulation, one workgroup per slice; dL/d(du_n) = ky_n dL/dphi_n.
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void k_row_phase_grad(Geo g, Tab<R> t, int stype, const void* __restrict__ samples,
+                                                       const cplx<R>* __restrict__ grad_s, R* __restrict__ grad_phase,
+                                                       R* __restrict__ grad_dalong) {
+  const int n = blockIdx.x;
+  const size_t base = (size_t)n * g.n_freq;
+  double acc = 0.0;
+  for (int p = threadIdx.x; p < g.n_freq; p += NT) {
+    const cplx<R> sv = load_sample<R>(samples, stype, base + p);
+    const cplx<R> gv = grad_s[base + p];
+    acc += (double)gv.y * (double)sv.x - (double)gv.x * (double)sv.y;
+  }
+  const double tot = block_sum<NT>(acc);
+  if (threadIdx.x == 0) {
+    grad_phase[n] = (R)tot;
+    if (grad_dalong) grad_dalong[n] = (R)((double)t.ky[n] * tot);
+  }
+}
+
 // ============================================================================ weights
 template <typename R, int NT>
 __global__ __launch_bounds__(NT) void k_weights(Geo g, Tab<R> t, R* __restrict__ w,
@@ -1067,8 +1099,8 @@ __global__ __launch_bounds__(NT) void k_weights(Geo g, Tab<R> t, R* __restrict__
   for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < total; i += (size_t)gridDim.x * NT) {
     const int n = (int)(i / g.n_freq), p = (int)(i - (size_t)n * g.n_freq);
     const double ku = t.ku[n];
-    const double lam = lattice_coord(stolt_kx(t.k[p], ku), g);
-    const R v = diag_weight<R>(g, t, t.poly, ku, p, lam);
+    const double lam = lattice_coord(kx_of(t, raw_k(t, g.n_freq, n, p), ku), g);
+    const R v = diag_weight<R>(g, t, t.poly, ku, n, p, lam);
     if (w) w[i] = v;
     kept += (v != (R)0) ? 1ull : 0ull;
   }
@@ -1096,7 +1128,7 @@ __global__ __launch_bounds__(NT) void k_ffr_taps(Geo g, Tab<R> t, double* __rest
   const int K = (int)ceil(g.q) + 1, KT = 2 * K + 1;
   for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < total; i += (size_t)gridDim.x * NT) {
     const int n = (int)(i / g.n_freq), p = (int)(i - (size_t)n * g.n_freq);
-    const double lam = lattice_coord(stolt_kx(t.k[p], t.ku[n]), g);
+    const double lam = lattice_coord(kx_of(t, raw_k(t, g.n_freq, n, p), t.ku[n]), g);
     const double f = floor(lam), delta = lam - f;
     fl[i] = (int)f;
     double sd, cd;
@@ -1493,6 +1525,14 @@ hipError_t launch_adj_rows(const Geo& g, const Tab<R>& t, int stype, const cplx<
 }
 
 template <typename R>
+hipError_t launch_row_phase_grad(const Geo& g, const Tab<R>& t, int stype, const void* samples, const cplx<R>* grad_s,
+                                 R* grad_phase, R* grad_dalong, hipStream_t st) {
+  hipLaunchKernelGGL((k_row_phase_grad<R, 256>), dim3(g.n_pulses), dim3(256), 0, st, g, t, stype, samples, grad_s,
+                     grad_phase, grad_dalong);
+  return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_weights(const Geo& g, const Tab<R>& t, R* w, unsigned long long* kept_partial, int nblocks,
                           hipStream_t st) {
   hipLaunchKernelGGL((k_weights<R, 256>), dim3(nblocks), dim3(256), 0, st, g, t, w, kept_partial);
@@ -1594,6 +1634,8 @@ hipError_t launch_fft(int log2n, int batch, int sign, const cplx<R>* in, cplx<R>
                                          cplx<R>*, cplx<R>*, hipStream_t);                                     \
   template hipError_t launch_adj_rows<R>(const Geo&, const Tab<R>&, int, const cplx<R>*, const void*, const R*, \
                                          const R*, const R*, cplx<R>*, R*, R*, const EntComb<R>&, hipStream_t); \
+  template hipError_t launch_row_phase_grad<R>(const Geo&, const Tab<R>&, int, const void*, const cplx<R>*, R*, R*, \
+                                               hipStream_t);                                                  \
   template hipError_t launch_weights<R>(const Geo&, const Tab<R>&, R*, unsigned long long*, int, hipStream_t);  \
   template hipError_t launch_ffr<R>(const Geo&, const Tab<R>&, double*, R*, int*, hipStream_t);                \
   template hipError_t launch_entropy<R>(const Geo&, const cplx<R>*, double*, int, double*, cplx<R>*,          \

@@ -37,6 +37,14 @@ def tffr_validate(params, k, ku):
     return _lib.load().tffr_validate(ctypes.byref(params), _dptr(k), _dptr(ku))
 
 
+def tffr_validate_xy(params, kx, ky):
+    kx = np.ascontiguousarray(kx, dtype=np.float64)
+    ky = np.ascontiguousarray(ky, dtype=np.float64)
+    if kx.shape != (params.n_pulses, params.n_freq) or ky.shape != kx.shape:
+        raise ValueError("kx / ky must be [n_pulses][n_freq]")
+    return _lib.load().tffr_validate_xy(ctypes.byref(params), _dptr(kx), _dptr(ky))
+
+
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
@@ -48,19 +56,32 @@ def _stream():
 class Plan:
     """tffr_plan_create / tffr_plan_destroy, and the calls that take a plan."""
 
-    def __init__(self, params, k, ku, device="cuda:0"):
+    def __init__(self, params, k, ku, device="cuda:0", kx=None, ky=None):
+        """Plan from radar wavenumbers k [n_freq], ku [n_pulses] (Stolt map), or, with k and
+        ku None, from explicit coordinates kx, ky [n_pulses][n_freq] (tffr_plan_create_xy)."""
         self.lib = _lib.load()
         self.params = params
         self.device = torch.device(device)
-        self.k = np.ascontiguousarray(k, dtype=np.float64)
-        self.ku = np.ascontiguousarray(ku, dtype=np.float64)
-        if self.k.size != params.n_freq or self.ku.size != params.n_pulses:
-            raise ValueError("k / ku sizes do not match params")
         self.ctype, self.rtype = _DT[params.dtype]
         h = ctypes.c_void_p()
-        with torch.cuda.device(self.device):
-            _lib.check(self.lib.tffr_plan_create(ctypes.byref(params), _dptr(self.k), _dptr(self.ku),
-                                                 ctypes.byref(h)), "tffr_plan_create")
+        if kx is not None:
+            self.kx = np.ascontiguousarray(kx, dtype=np.float64)
+            kyv = np.ascontiguousarray(ky, dtype=np.float64)
+            if self.kx.shape != (params.n_pulses, params.n_freq) or kyv.shape != self.kx.shape:
+                raise ValueError("kx / ky must be [n_pulses][n_freq]")
+            self.k, self.ku = None, kyv[:, 0].copy()
+            with torch.cuda.device(self.device):
+                _lib.check(self.lib.tffr_plan_create_xy(ctypes.byref(params), _dptr(self.kx), _dptr(kyv),
+                                                        ctypes.byref(h)), "tffr_plan_create_xy")
+        else:
+            self.kx = None
+            self.k = np.ascontiguousarray(k, dtype=np.float64)
+            self.ku = np.ascontiguousarray(ku, dtype=np.float64)
+            if self.k.size != params.n_freq or self.ku.size != params.n_pulses:
+                raise ValueError("k / ku sizes do not match params")
+            with torch.cuda.device(self.device):
+                _lib.check(self.lib.tffr_plan_create(ctypes.byref(params), _dptr(self.k), _dptr(self.ku),
+                                                     ctypes.byref(h)), "tffr_plan_create")
         self.handle = h
         nfx, nfy, hb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         beta = ctypes.c_double()
@@ -136,6 +157,16 @@ class Plan:
                                          _ptr(user_w), _ptr(out), _ptr(gph), _ptr(gda), _ptr(self.work),
                                          _stream()), "tffr_adjoint")
         return out, gph, gda
+
+    def tffr_row_phase_grad(self, samples, grad_samples, want_dalong=True):
+        """Per-slice (dL/dphi, dL/d du) from a sample cotangent computed elsewhere."""
+        self._chk_samples(samples)
+        self._chk(grad_samples, self.shape_samples, self.ctype, "grad_samples")
+        gph = torch.empty(self.params.n_pulses, dtype=self.rtype, device=self.device)
+        gda = torch.empty(self.params.n_pulses, dtype=self.rtype, device=self.device) if want_dalong else None
+        _lib.check(self.lib.tffr_row_phase_grad(self.handle, _ptr(samples), _ptr(grad_samples), _ptr(gph),
+                                                _ptr(gda), _stream()), "tffr_row_phase_grad")
+        return gph, gda
 
     def tffr_entropy(self, image, want_grad=True):
         self._chk(image, self.shape_image, self.ctype, "image")

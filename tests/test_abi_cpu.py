@@ -95,6 +95,29 @@ def test_validate_geometry_errors():
     assert T.tffr_validate(p, kk, ku) == 1
 
 
+def test_validate_xy_layout_and_order():
+    """Explicit coordinates: ky must be one value along each slice (TFFR_ERR_LAYOUT),
+    kx strictly increasing along it (TFFR_ERR_NONMONOTONE), values finite (TFFR_ERR_ARG)."""
+    k, ku = scenes.radar_sampling(8, 16)
+    p = _ok_params()
+    kx = np.sqrt(4 * k[None, :] ** 2 - ku[:, None] ** 2)
+    ky = np.repeat(ku[:, None], 16, axis=1)
+    assert T.tffr_validate_xy(p, kx, ky) == 0
+    bad = ky.copy()
+    bad[2, 7] += 1e-9
+    assert T.tffr_validate_xy(p, kx, bad) == 4
+    bad = kx.copy()
+    bad[5, 9] = bad[5, 8]
+    assert T.tffr_validate_xy(p, bad, ky) == 3
+    bad = kx.copy()
+    bad[1, 1] = np.inf
+    assert T.tffr_validate_xy(p, bad, ky) == 1
+    # non-Stolt geometry with the slice structure is accepted
+    rng = np.random.default_rng(0)
+    jit = kx + rng.uniform(-0.1, 0.1, kx.shape) * np.diff(kx, axis=1).min()
+    assert T.tffr_validate_xy(p, jit, ky) == 0
+
+
 def test_status_strings():
     lib = _lib.load()
     for code, name in _lib.STATUS_NAMES.items():
@@ -108,10 +131,15 @@ def test_null_handles_are_rejected_without_device():
     assert lib.tffr_adjoint(None, None, None, None, None, None, None, None, None, None, None) == 1
     assert lib.tffr_entropy(None, None, None, None, None, None) == 1
     assert lib.tffr_weights(None, None, None, None) == 1
+    assert lib.tffr_row_phase_grad(None, None, None, None, None, None) == 1
     assert lib.tffr_debug_fft(3, 1, 1, 0, None, None, None) == 1
     out = ctypes.c_void_p()
     k, ku = scenes.radar_sampling(8, 16)
     bad = _ok_params(n_pulses=0)
     assert lib.tffr_plan_create(ctypes.byref(bad), k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                 ku.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(out)) == 1
+    assert not out.value
+    kx = np.ones((8, 16))
+    assert lib.tffr_plan_create_xy(ctypes.byref(bad), kx.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   kx.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(out)) == 1
     assert not out.value

@@ -354,3 +354,78 @@ def test_graph_replays_match_eager(weighting):
         torch.cuda.synchronize()
         for a, b in zip(out, eager):
             assert torch.equal(a, b), f"replay {rep}"
+
+
+# ---------------------------------------------------------------- explicit coordinates
+@pytest.mark.parametrize("dtype,width", [(T.C64, 7), (T.C128, 14)])
+def test_plan_from_coordinates_equals_stolt_plan(dtype, width):
+    """tffr_plan_create_xy with the Stolt map's own coordinates: the same image and
+    gradients as the plan made from (k, ku) (the host forms kx with the kernels'
+    operation order, so the values and every kernel decision coincide)."""
+    print(f"xy plan == Stolt plan, dtype={dtype}", flush=True)
+    case = Case(16, 200, 64, fov=40.0, dtype=dtype, width=width, seed=21)
+    kx, ky, lam, X, Y = case.prob.geometry()
+    pxy = T.Plan(case.prm, None, None, DEV, kx=kx, ky=np.repeat(ky[:, None], kx.shape[1], axis=1))
+    s, st = case.samples()
+    ph = case.real(case.rng.normal(0, 0.5, 16))
+    da = case.real(case.rng.normal(0, 0.004, 16))
+    a = case.plan.tffr_forward(st, ph, da)
+    b = pxy.tffr_forward(st, ph, da)
+    assert torch.equal(a, b)
+    ga = case.plan.tffr_entropy_step(st, ph, da)
+    gb = pxy.tffr_entropy_step(st, ph, da)
+    for x, y in zip(ga, gb):
+        assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("weighting", [T.W_TFFR, T.W_QUAD, T.W_NONE, T.W_FFR])
+def test_plan_from_jittered_coordinates_vs_oracle(weighting):
+    """A non-Stolt geometry with the slice structure (kx jittered along every slice,
+    ky shifted): forward and adjoint against the oracle on the same coordinates."""
+    print(f"xy plan, jittered geometry, weighting={weighting}", flush=True)
+    case = Case(12, 100, 64, fov=40.0, weighting=weighting, seed=22)
+    kx, ky, lam, X, Y = case.prob.geometry()
+    rng = np.random.default_rng(23)
+    jit = kx + rng.uniform(-0.3, 0.3, kx.shape) * np.min(np.diff(kx, axis=1))
+    kyj = ky + 0.37
+    plan = T.Plan(case.prm, None, None, DEV, kx=jit, ky=np.repeat(kyj[:, None], kx.shape[1], axis=1))
+    prob = OP.Problem(k=case.k, ku=case.ku, mx=64, my=64, fov_x=40.0, fov_y=40.0, weighting=weighting,
+                      kx_explicit=jit, ky_explicit=kyj)
+    s, st = case.samples()
+    phase = case.rng.normal(0, 0.5, 12)
+    dal = case.rng.normal(0, 0.004, 12)
+    got = plan.tffr_forward(st, case.real(phase), case.real(dal)).cpu().numpy()
+    ref = OP.image(prob, s, case.rounded(phase), case.rounded(dal))
+    e = rel_l2(got, ref)
+    y = case.image_np()
+    yt = torch.as_tensor(y, dtype=case.ctype, device=DEV)
+    gs, gph, gda = plan.tffr_adjoint(yt, st, case.real(phase), case.real(dal), want_phase=True, want_dalong=True)
+    rgs, rgph, rgda = OP.backward(prob, yt.cpu().numpy().astype(np.complex128), s, case.rounded(phase),
+                                  case.rounded(dal))
+    e1 = rel_l2(gs.cpu().numpy(), rgs)
+    e2 = np.max(np.abs(gph.cpu().numpy() - rgph)) / np.max(np.abs(rgph))
+    e3 = np.max(np.abs(gda.cpu().numpy() - rgda)) / np.max(np.abs(rgda))
+    print(f"  forward {e:.3e}  grad_s {e1:.3e}  dphi {e2:.3e}  ddu {e3:.3e}", flush=True)
+    assert e < 1e-5 and e1 < 1e-5 and e2 < 2e-4 and e3 < 2e-4
+
+
+@pytest.mark.parametrize("dtype", [T.C64, T.C128, T.C64_FP16IN])
+def test_row_phase_grad(dtype):
+    """tffr_row_phase_grad on the adjoint's sample cotangent reproduces the phase and
+    position gradients the adjoint reduces itself, and the oracle's."""
+    print(f"row phase grad dtype={dtype}", flush=True)
+    case = Case(10, 150, 32, dtype=dtype, width=7 if dtype != T.C128 else 14, seed=24)
+    s, st = case.samples()
+    phase = case.rng.normal(0, 0.5, 10)
+    dal = case.rng.normal(0, 0.004, 10)
+    yt = torch.as_tensor(case.image_np(), dtype=case.ctype, device=DEV)
+    gs, gph, gda = case.plan.tffr_adjoint(yt, st, case.real(phase), case.real(dal), want_phase=True,
+                                          want_dalong=True)
+    gph2, gda2 = case.plan.tffr_row_phase_grad(st, gs)
+    scale = float(gph.abs().max())
+    assert float((gph2 - gph).abs().max()) <= 1e-6 * scale
+    assert float((gda2 - gda).abs().max()) <= 1e-6 * float(gda.abs().max())
+    # the formula itself, in FP64 on the same inputs
+    gsn = gs.cpu().numpy().astype(np.complex128)
+    ref = np.sum(gsn.imag * s.real - gsn.real * s.imag, axis=1)
+    assert np.max(np.abs(gph2.cpu().numpy() - ref)) <= 1e-5 * np.max(np.abs(ref))

@@ -165,6 +165,28 @@ def test_k4_forms_match_brute_force():
     assert abs(got[0] - full[3, 9]) / abs(full[3, 9]) < 50 * tol
 
 
+def test_explicit_coordinates():
+    """A problem given by explicit coordinates: equal to the Stolt problem when the
+    coordinates are the Stolt map's, and, for a jittered non-Stolt geometry, equal to the
+    brute-force sum with the tFFR weights of its own lattice coordinates."""
+    rng = np.random.default_rng(9)
+    prob = _tiny_problem(6, 12, 16)
+    kx, ky, lam, X, Y = prob.geometry()
+    s = rng.standard_normal(kx.shape) + 1j * rng.standard_normal(kx.shape)
+    same = pipeline.Problem(k=prob.k, ku=prob.ku, mx=16, my=16, fov_x=40.0, fov_y=40.0, kx_explicit=kx,
+                            ky_explicit=ky)
+    assert np.array_equal(pipeline.image(same, s), pipeline.image(prob, s))
+    jit = kx + rng.uniform(-0.3, 0.3, kx.shape) * np.min(np.diff(kx, axis=1))
+    kyj = ky + 0.01
+    other = pipeline.Problem(k=prob.k, ku=prob.ku, mx=16, my=16, fov_x=40.0, fov_y=40.0, kx_explicit=jit,
+                             ky_explicit=kyj)
+    lamj = jit * 40.0 / (2 * np.pi)
+    d = np.array([[1.0 / weights.frame_diagonal(v - np.floor(v), 0.01, 3.0) for v in row] for row in lamj])
+    ref = brute_force_image(d * s, jit, kyj, X, Y)
+    tol = 4 * np.finfo(float).eps * np.max(np.abs(jit)) * np.max(np.abs(X)) * 2
+    assert _rel(pipeline.image(other, s), ref) < tol
+
+
 # ---------------------------------------------------------------- K5: window transforms
 def _quad_complex(f, lo, hi, points=None):
     re = integrate.quad(lambda x: np.real(f(x)), lo, hi, points=points, epsabs=1e-15, epsrel=1e-14, limit=400)[0]
