@@ -175,12 +175,17 @@ def main():
     dev = "cuda:0"
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    inp = scenes.make_inputs(wl, device=dev, scene=True)
+    if args.profile_steps:
+        # profiler runs: the kernels' work does not depend on the sample values, and a
+        # seeded random phase history keeps the traced process to a handful of launches
+        k, ku = scenes.radar_sampling(wl.n_pulses, wl.n_freq)
+        s = torch.as_tensor(scenes.random_samples(wl.n_pulses, wl.n_freq, 1), dtype=torch.complex64, device=dev)
+    else:
+        inp = scenes.make_inputs(wl, device=dev, scene=True)
+        k, ku = inp["k"], inp["ku"]
+        s = inp["samples"].to(torch.complex64).contiguous()
     torch.cuda.synchronize()
     t_synth = time.perf_counter() - t0
-    k, ku = inp["k"], inp["ku"]
-    s64 = inp["samples"]
-    s = s64.to(torch.complex64).contiguous()
     # autofocus-style estimates: start from zero phase / position error
     ph = torch.zeros(wl.n_pulses, dtype=torch.float32, device=dev)
     da = torch.zeros_like(ph)
@@ -206,41 +211,52 @@ def main():
                           "copy_bytes": profiling.COPY_BYTES}))
         return
 
-    ms, runner = time_step(torch, step, args.steps, args.warmup, graph=not args.eager)
-    # graph replays must reproduce the eager result
-    step()
-    torch.cuda.synchronize()
-    ref_img, ref_gph = step.img.clone(), step.gph.clone()
-    runner()
-    torch.cuda.synchronize()
-    replay_ok = bool(torch.equal(step.img, ref_img) or float((step.img - ref_img).abs().max()) <=
-                     1e-5 * float(ref_img.abs().max()))
-    replay_ok = replay_ok and float((step.gph - ref_gph).abs().max()) <= 1e-4 * float(ref_gph.abs().max() + 1e-30)
-    ms_eager = None
+    # the step timed both ways, as a HIP graph replay and as eager launches on one stream;
+    # `value` is the faster (config.timing names it), both are reported
+    ms_eager, _ = time_step(torch, step, args.steps, args.warmup, graph=False)
+    ms_graph, replay_ok = None, None
     if not args.eager:
-        ms_eager, _ = time_step(torch, step, max(10, args.steps // 4), 5, graph=False)
+        ms_graph, runner = time_step(torch, step, args.steps, args.warmup, graph=True)
+        # graph replays must reproduce the eager result
+        step()
+        torch.cuda.synchronize()
+        ref_img, ref_gph = step.img.clone(), step.gph.clone()
+        runner()
+        torch.cuda.synchronize()
+        replay_ok = bool(torch.equal(step.img, ref_img) or float((step.img - ref_img).abs().max()) <=
+                         1e-5 * float(ref_img.abs().max()))
+        replay_ok = replay_ok and float((step.gph - ref_gph).abs().max()) <= 1e-4 * float(
+            ref_gph.abs().max() + 1e-30)
+    use_graph = ms_graph is not None and ms_graph < ms_eager
+    ms = ms_graph if use_graph else ms_eager
 
-    # the two stage kernels, each timed alone through the per-stage entry points with the
-    # same launch configuration as inside tffr_forward; the slower one is reported
+    # the step's two forward-side kernels, each timed alone through the per-stage entry
+    # points with the launch configuration used inside tffr_entropy_step (the range
+    # kernel the plan picked; the fused entropy azimuth kernel); the slower is reported
     hx = torch.empty((wl.n_pulses, wl.m), dtype=torch.complex64, device=dev)
+    h2 = torch.empty_like(hx)
     img_k = torch.empty((wl.m, wl.m), dtype=torch.complex64, device=dev)
+    rows_name = "k_fwd_rows_run" if plan.range_mode == 1 else "k_fwd_rows"
 
     def range_stage():
         T._lib.check(plan.lib.tffr_debug_rows(plan.handle, 1, T._ptr(s), T._ptr(ph), T._ptr(da), None,
                                               T._ptr(hx), T._stream()))
 
     def azimuth_stage():
-        T._lib.check(plan.lib.tffr_debug_cols(plan.handle, T._ptr(hx), T._ptr(img_k), T._stream()))
+        T._lib.check(plan.lib.tffr_debug_ent_cols(plan.handle, T._ptr(hx), T._ptr(img_k), T._ptr(h2),
+                                                  T._ptr(plan.work), T._stream()))
 
+    range_stage()
     t_rows = kernel_time(torch, range_stage)
     t_cols = kernel_time(torch, azimuth_stage)
-    # algorithmic bytes per launch: samples in + range spectra out; range spectra in + image out
+    # algorithmic bytes per launch: samples in + range spectra out; range spectra in, image
+    # out, two adjoint range-spectra fields out
     bytes_rows = 8 * wl.n_samples + 8 * wl.n_pulses * wl.m
-    bytes_cols = 8 * wl.n_pulses * wl.m + 8 * wl.m * wl.m
+    bytes_cols = 24 * wl.n_pulses * wl.m + 8 * wl.m * wl.m
     if t_rows >= t_cols:
-        kname, t_k, alg_bytes = "k_fwd_rows", t_rows, bytes_rows
+        kname, t_k, alg_bytes = rows_name, t_rows, bytes_rows
     else:
-        kname, t_k, alg_bytes = "k_fwd_cols", t_cols, bytes_cols
+        kname, t_k, alg_bytes = "k_ent_cols", t_cols, bytes_cols
     achieved = alg_bytes / t_k / 1e9
     from paper_1910_10908_amd import profiling
 
@@ -265,14 +281,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "n_pulses": wl.n_pulses, "n_freq": wl.n_freq, "image": [wl.m, wl.m],
                    "fine_grid": list(plan.nfine), "kernel_width": width, "weighting": "tffr", "tau": 0.97,
-                   "window_a": 0.01, "q": 3, "timing": "eager" if args.eager else "hip_graph",
+                   "window_a": 0.01, "q": 3, "timing": "hip_graph" if use_graph else "eager",
                    "parallelism": "single_gpu"},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel_us": t_k * 1e6,
-                     "alg_bytes": alg_bytes, "stage_us": {"k_fwd_rows": t_rows * 1e6, "k_fwd_cols": t_cols * 1e6}},
+                     "alg_bytes": alg_bytes, "stage_us": {rows_name: t_rows * 1e6, "k_ent_cols": t_cols * 1e6}},
         "kept_count": kept,
         "graph_replay_matches_eager": replay_ok,
         "eager_ms_per_step": ms_eager,
+        "graph_ms_per_step": ms_graph,
         "input_synthesis_s": t_synth,
     }
 

@@ -33,6 +33,23 @@ tffr_status tffr_debug_rows(tffr_plan *plan, int32_t stage, const void *d_sample
  * tffr_forward. */
 tffr_status tffr_debug_cols(tffr_plan *plan, const void *d_hx, void *d_image, tffr_stream stream);
 
+/* Launch configuration the plan chose: range_mode 0 (sub-pass gridding) or 1
+ * (sliding-window runs, dense slices); az_cols range columns per azimuth workgroup;
+ * ent_fused 1 when tffr_entropy_step uses the fused azimuth kernel.  Any pointer may be
+ * NULL. */
+tffr_status tffr_debug_plan_config(const tffr_plan *plan, int32_t *range_mode, int32_t *az_cols,
+                                   int32_t *ent_fused);
+
+/* Azimuth stage of the fused entropy step alone (the launch inside tffr_entropy_step):
+ *   d_hx     [n_pulses][mx] range spectra in; overwritten with the adjoint azimuth
+ *            transform of I (ln|I|^2 - c_b), c_b = ln of column block b's mean |I|^2
+ *   d_image  [mx][my] written (as tffr_debug_cols)
+ *   d_h2     [n_pulses][mx] written: adjoint azimuth transform of I
+ *   d_work   workspace of the plan (receives the entropy partial sums and the c_b)
+ * TFFR_ERR_UNSUPPORTED when the plan's entropy step does not use the fused kernel. */
+tffr_status tffr_debug_ent_cols(tffr_plan *plan, void *d_hx, void *d_image, void *d_h2,
+                                void *d_work, tffr_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

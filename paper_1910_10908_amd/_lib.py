@@ -62,6 +62,9 @@ _PROTOS = {
     "tffr_debug_fft": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]),
     "tffr_debug_rows": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tffr_debug_cols": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "tffr_debug_ent_cols": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "tffr_debug_plan_config": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_int32)]),
 }
 
 _lib = None

@@ -872,4 +872,28 @@ tffr_status tffr_debug_cols(tffr_plan* P, const void* hx, void* img, tffr_stream
   return hip_status(e);
 }
 
+tffr_status tffr_debug_plan_config(const tffr_plan* P, int32_t* range_mode, int32_t* az_cols, int32_t* ent_fused) {
+  if (!P) return TFFR_ERR_ARG;
+  if (range_mode) *range_mode = P->geo.range_mode;
+  if (az_cols) *az_cols = P->cb;
+  if (ent_fused) *ent_fused = P->ent_fused ? 1 : 0;
+  return TFFR_OK;
+}
+
+tffr_status tffr_debug_ent_cols(tffr_plan* P, void* hx, void* img, void* h2, void* work, tffr_stream stream) {
+  if (!P || !hx || !img || !h2 || !work) return TFFR_ERR_ARG;
+  if (!P->ent_fused) return TFFR_ERR_UNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  char* wb = (char*)work;
+  double* part = (double*)(wb + P->off_part);
+  hipError_t e =
+      P->dbl() ? tffr::launch_ent_cols<double>(P->geo, tables<double>(P), P->cb, (const cplx<double>*)hx,
+                                               (cplx<double>*)img, part, (double*)(wb + P->off_cblk),
+                                               (cplx<double>*)hx, (cplx<double>*)h2, st)
+               : tffr::launch_ent_cols<float>(P->geo, tables<float>(P), P->cb, (const cplx<float>*)hx,
+                                              (cplx<float>*)img, part, (float*)(wb + P->off_cblk),
+                                              (cplx<float>*)hx, (cplx<float>*)h2, st);
+  return hip_status(e);
+}
+
 }  // extern "C"

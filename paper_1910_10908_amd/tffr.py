@@ -91,6 +91,9 @@ class Plan:
         self.beta = beta.value
         self.ffr_halfband = hb.value
         self.work = torch.empty(int(self.lib.tffr_workspace_bytes(h)), dtype=torch.uint8, device=self.device)
+        rm, cb, fu = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(self.lib.tffr_debug_plan_config(h, ctypes.byref(rm), ctypes.byref(cb), ctypes.byref(fu)))
+        self.range_mode, self.az_cols, self.ent_fused = rm.value, cb.value, bool(fu.value)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -232,6 +235,19 @@ def tffr_debug_cols(plan, hx, out=None):
         out = torch.empty(plan.shape_image, dtype=plan.ctype, device=plan.device)
     _lib.check(plan.lib.tffr_debug_cols(plan.handle, _ptr(hx), _ptr(out), _stream()), "tffr_debug_cols")
     return out
+
+
+def tffr_debug_ent_cols(plan, hx):
+    """Fused entropy-step azimuth stage alone: range spectra -> (image, h1, h2), where h1
+    and h2 are the adjoint azimuth transforms of I (ln|I|^2 - c_b) and of I; hx is left
+    unchanged (the kernel works on a copy)."""
+    plan._chk(hx, (plan.params.n_pulses, plan.params.mx), plan.ctype, "hx")
+    h1 = hx.clone()
+    img = torch.empty(plan.shape_image, dtype=plan.ctype, device=plan.device)
+    h2 = torch.empty_like(hx)
+    _lib.check(plan.lib.tffr_debug_ent_cols(plan.handle, _ptr(h1), _ptr(img), _ptr(h2), _ptr(plan.work),
+                                            _stream()), "tffr_debug_ent_cols")
+    return img, h1, h2
 
 
 def tffr_debug_fft(x, sign):

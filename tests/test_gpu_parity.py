@@ -429,3 +429,36 @@ def test_row_phase_grad(dtype):
     gsn = gs.cpu().numpy().astype(np.complex128)
     ref = np.sum(gsn.imag * s.real - gsn.real * s.imag, axis=1)
     assert np.max(np.abs(gph2.cpu().numpy() - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("size", [(64, 128, 128), (33, 100, 50)])
+def test_fused_azimuth_stage_fields(size):
+    """The entropy step's fused azimuth kernel alone: its image equals the forward
+    azimuth kernel's bit for bit, and its two adjoint fields are the adjoint azimuth
+    transforms (FP64 reference of the type-2 sum over the image pixels) of I and of
+    I (ln|I|^2 - c_b), with c_b = ln of the block's mean |I|^2."""
+    print(f"fused azimuth stage size={size}", flush=True)
+    case = Case(*size, seed=31)
+    s, st = case.samples()
+    hx = case.plan.tffr_debug_rows(st, stage=1)
+    img_ref = T.tffr_debug_cols(case.plan, hx)
+    img, h1, h2 = T.tffr_debug_ent_cols(case.plan, hx)
+    assert torch.equal(img, img_ref)
+    kx, ky, lam, X, Y = case.prob.geometry()
+    I = img.cpu().numpy().astype(np.complex128)
+    # adjoint azimuth transform: h[n][jx] = sum_jy f[jx][jy] exp(-i ky_n Y_jy)
+    E = np.exp(-1j * np.outer(ky, Y))  # [n_pulses][my]
+    r2 = (E @ I.T)
+    assert rel_l2(h2.cpu().numpy(), r2) < 1e-5
+    a = np.abs(I) ** 2
+    mx, my = case.prm.mx, case.prm.my
+    lg = np.where(a > 0, np.log(np.where(a > 0, a, 1.0)), 0.0)
+    # the kernel centres per column block; the block width is the plan's (1, 2 or 4):
+    # find the one that reproduces h1 (each block's constant is fixed by the image alone)
+    best = 1.0
+    for w in (1, 2, 4):
+        cbk = np.array([np.log(a[j0:j0 + w].sum() / (min(w, mx - j0) * my)) for j0 in range(0, mx, w)])
+        cc = np.repeat(cbk, w)[:mx]
+        r1 = E @ (I * (lg - cc[:, None])).T
+        best = min(best, rel_l2(h1.cpu().numpy(), r1))
+    assert best < 1e-5
