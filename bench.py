@@ -190,9 +190,9 @@ def main():
     ph = torch.zeros(wl.n_pulses, dtype=torch.float32, device=dev)
     da = torch.zeros_like(ph)
 
-    def params(weighting, w=width):
+    def params(weighting, w=width, gridding=T.GRID_ES):
         return T.default_params(n_pulses=wl.n_pulses, n_freq=wl.n_freq, mx=wl.m, my=wl.m, fov_x=wl.fov,
-                                fov_y=wl.fov, weighting=weighting, kernel_width=w, dtype=T.C64)
+                                fov_y=wl.fov, weighting=weighting, kernel_width=w, dtype=T.C64, gridding=gridding)
 
     plan = T.Plan(params(T.W_TFFR), k, ku, dev)
     step = Step(T, plan, s, ph, da)
@@ -295,10 +295,12 @@ def main():
 
     if not args.no_compare:
         comp = {}
-        for name, wt, w in (("plain_ffr", T.W_FFR, width), ("plain_nufft_quad", T.W_QUAD, width),
-                            ("tffr_width6", T.W_TFFR, 6)):
+        for name, wt, w, gr in (("plain_ffr", T.W_FFR, width, T.GRID_ES),
+                                ("plain_nufft_quad", T.W_QUAD, width, T.GRID_ES),
+                                ("tffr_width6", T.W_TFFR, 6, T.GRID_ES),
+                                ("tffr_literal_algorithm1", T.W_TFFR, width, T.GRID_LITERAL)):
             try:
-                p2 = T.Plan(params(wt, w), k, ku, dev)
+                p2 = T.Plan(params(wt, w, gr), k, ku, dev)
             except RuntimeError as e:
                 comp[name] = {"error": str(e)}
                 continue
@@ -308,6 +310,9 @@ def main():
                           "kernel_width": w}
             if wt == T.W_FFR:
                 comp[name]["note"] = "banded D = B_2(pinv(Psi W)) solved on the GPU inside every step"
+            if gr == T.GRID_LITERAL:
+                comp[name]["note"] = ("range gridding with the window's own transform truncated to |l - lam| < q "
+                                      "on the image lattice, / w(x) (Eq. (8) as printed); azimuth as tFFR")
             del p2, st2
         out["comparisons"] = comp
 
@@ -324,11 +329,13 @@ def main():
         pk = 20 * np.log10(np.max(np.abs(got - ref_cols)) / np.max(np.abs(ref_cols)))
         out["accuracy"] = {"rel_l2_vs_fp64": float(err), "peak_db": float(pk),
                            "sample": f"{len(col_idx)} of {wl.m} image columns, full height"}
-        if "comparisons" in out and "tffr_width6" in out["comparisons"]:
-            p6 = T.Plan(params(T.W_TFFR, 6), k, ku, dev)
-            img6 = p6.tffr_forward(s, ph, da).cpu().numpy()[col_idx].astype(np.complex128)
-            out["comparisons"]["tffr_width6"]["rel_l2_vs_fp64"] = float(
-                np.linalg.norm(img6 - ref_cols) / np.linalg.norm(ref_cols))
+        for name, prm in (("tffr_width6", params(T.W_TFFR, 6)),
+                          ("tffr_literal_algorithm1", params(T.W_TFFR, width, T.GRID_LITERAL))):
+            if "comparisons" in out and "error" not in out["comparisons"].get(name, {"error": 1}):
+                p6 = T.Plan(prm, k, ku, dev)
+                img6 = p6.tffr_forward(s, ph, da).cpu().numpy()[col_idx].astype(np.complex128)
+                out["comparisons"][name]["rel_l2_vs_fp64"] = float(
+                    np.linalg.norm(img6 - ref_cols) / np.linalg.norm(ref_cols))
     print(json.dumps(out), flush=True)
 
 

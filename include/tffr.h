@@ -74,6 +74,15 @@ enum { TFFR_THRESH_LITERAL = 0, TFFR_THRESH_CORRELATION = 1 };
 
 enum { TFFR_C64 = 0, TFFR_C128 = 1, TFFR_C64_FP16IN = 2 };
 
+/* Range gridding.  TFFR_GRID_ES: exponential-of-semicircle kernel on a grid upsampfac
+ * times finer than the image, deapodised by the kernel's transform; approximates the
+ * weighted sum of Eq. (1) to ~1e-6 at width 7.  TFFR_GRID_LITERAL: Algorithm 1 / Eq. (8)
+ * as printed: the window's own transform R_W(l_m - lambda) at the 2q lattice points
+ * |l_m - lambda| < q of the image lattice itself (no oversampling), inverse FFT, division
+ * by w(x) = exp(-a |x - 1/2|); the truncation error of the paper's method is kept.  The
+ * azimuth stage is the same in both. */
+enum { TFFR_GRID_ES = 0, TFFR_GRID_LITERAL = 1 };
+
 typedef struct {
   int32_t n_pulses;     /* slices n (azimuth), >= 1                                   */
   int32_t n_freq;       /* samples p per slice (fast-time frequency), >= 1            */
@@ -88,6 +97,8 @@ typedef struct {
   int32_t kernel_width; /* gridding taps: 2..16 (7 gives ~1e-6 relative error)        */
   double upsampfac;     /* fine grid >= upsampfac * image size, rounded up to 2^k; 1.25..4 */
   int32_t dtype;        /* TFFR_C64, TFFR_C128, TFFR_C64_FP16IN                        */
+  int32_t gridding;     /* TFFR_GRID_ES (default) or TFFR_GRID_LITERAL (integer q <= 8,
+                           mx a power of two >= 64)                                    */
 } tffr_params;
 
 /* Paper defaults: a = 0.01, tau = 0.97, r = 2 (Sec. IV, Baselines); q = 3, tFFR with

@@ -21,9 +21,11 @@ Frame-Based Reconstruction for Stripmap SAR"):
 * pipeline   -- sample phasing by per-pulse phase / along-track errors, weighting,
                 imaging, and the gradients of an image loss through the adjoint.
 * entropy    -- image entropy loss and its gradient.
+* literal    -- the range gridding of Algorithm 1 / Eq. (8) taken literally: the window's
+                own truncated transform on the image lattice, inverse DFT, division by w.
 
 Where the paper is ambiguous or garbled, the reading taken is stated in the docstring of
 the function that takes it.
 """
 
-from . import geometry, window, weights, nudft, pipeline, entropy  # noqa: F401
+from . import geometry, window, weights, nudft, pipeline, entropy, literal  # noqa: F401

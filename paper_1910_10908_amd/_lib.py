@@ -17,6 +17,7 @@ STATUS_NAMES = {0: "TFFR_OK", 1: "TFFR_ERR_ARG", 2: "TFFR_ERR_EVANESCENT", 3: "T
 W_NONE, W_QUAD, W_FFR, W_TFFR, W_USER = 0, 1, 2, 3, 4
 THRESH_LITERAL, THRESH_CORRELATION = 0, 1
 C64, C128, C64_FP16IN = 0, 1, 2
+GRID_ES, GRID_LITERAL = 0, 1
 
 
 class Params(ctypes.Structure):
@@ -36,6 +37,7 @@ class Params(ctypes.Structure):
         ("kernel_width", ctypes.c_int32),
         ("upsampfac", ctypes.c_double),
         ("dtype", ctypes.c_int32),
+        ("gridding", ctypes.c_int32),
     ]
 
 

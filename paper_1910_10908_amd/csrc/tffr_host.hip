@@ -263,6 +263,12 @@ tffr_status check_params(const tffr_params* p) {
   if (p->dtype != TFFR_C64 && p->dtype != TFFR_C128 && p->dtype != TFFR_C64_FP16IN) return TFFR_ERR_UNSUPPORTED;
   const int lx = log2_pow2_at_least(p->upsampfac * p->mx), ly = log2_pow2_at_least(p->upsampfac * p->my);
   if (std::max(lx, 6) > kMaxLogN || std::max(ly, 6) > kMaxLogN) return TFFR_ERR_UNSUPPORTED;
+  if (p->gridding != TFFR_GRID_ES && p->gridding != TFFR_GRID_LITERAL) return TFFR_ERR_ARG;
+  if (p->gridding == TFFR_GRID_LITERAL) {
+    // the image lattice is the range grid: a power of two the LDS FFT handles; 2q taps
+    if (p->q != std::floor(p->q) || p->q > 8.0) return TFFR_ERR_UNSUPPORTED;
+    if (p->mx < 64 || (p->mx & (p->mx - 1))) return TFFR_ERR_UNSUPPORTED;
+  }
   return TFFR_OK;
 }
 
@@ -380,9 +386,10 @@ bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 // under kDenseSpacing cells apart; each of its threads takes at most one run per part.
 constexpr double kDenseSpacing = 2.5;
 
-void range_schedule(const tffr_params* p, const HostKx& kx, int nfx, int nt, int* S, int* part_len, int* mode) {
+void range_schedule(const tffr_params* p, const HostKx& kx, int nfx, int W, int nt, int* S, int* part_len,
+                    int* mode) {
   const double tx = p->fov_x / (2.0 * kPi * p->mx);
-  const int P = p->n_freq, W = p->kernel_width;
+  const int P = p->n_freq;
   double smin = 1e300, smax = 0.0;
   int Q = 1;
   std::vector<double> U(P);
@@ -409,7 +416,8 @@ void range_schedule(const tffr_params* p, const HostKx& kx, int nfx, int nt, int
   }
   *S = std::max(1, s);
   int m = (P > 1 && W <= tffr::kRunWindow && smax < kDenseSpacing) ? 1 : 0;
-  if (const char* e = std::getenv("TFFR_RANGE_MODE")) {
+  if (p->gridding == TFFR_GRID_LITERAL) m = 0;  // lattice taps: sub-pass kernel only
+  else if (const char* e = std::getenv("TFFR_RANGE_MODE")) {
     const int v = std::atoi(e);
     if (v == 0 || (v == 1 && W <= tffr::kRunWindow)) m = v;
   }
@@ -436,6 +444,7 @@ void tffr_default_params(tffr_params* p) {
   p->kernel_width = 7;
   p->upsampfac = 2.0;
   p->dtype = TFFR_C64;
+  p->gridding = TFFR_GRID_ES;
 }
 
 const char* tffr_status_string(tffr_status s) {
@@ -511,12 +520,14 @@ tffr_status plan_create(const tffr_params* p, const double* k, const double* ku,
   if (hipGetDevice(&P->device) != hipSuccess) return fail(TFFR_ERR_HIP);
 
   const int W = p->kernel_width;
-  const int lognx = std::max(6, log2_pow2_at_least(p->upsampfac * p->mx));
+  const bool lit = p->gridding == TFFR_GRID_LITERAL;
+  // range grid: the oversampled ES grid, or the image lattice itself (literal Algorithm 1)
+  const int lognx = lit ? log2_pow2_at_least(p->mx) : std::max(6, log2_pow2_at_least(p->upsampfac * p->mx));
   const int logny = std::max(6, log2_pow2_at_least(p->upsampfac * p->my));
   const int nfx = 1 << lognx, nfy = 1 << logny;
   // ES shape for the achieved upsampling factor: beta = 2.30 W at sigma = 2, scaled
   // for other sigma with the usual (1 - 1/(2 sigma)) law.
-  const double sig = std::min((double)nfx / p->mx, (double)nfy / p->my);
+  const double sig = lit ? (double)nfy / p->my : std::min((double)nfx / p->mx, (double)nfy / p->my);
   P->beta = 2.30 * W * (1.0 - 1.0 / (2.0 * sig)) / 0.75;
   const size_t csz = P->csize();
   const size_t lds_max = tffr::max_dynamic_lds();
@@ -551,6 +562,8 @@ tffr_status plan_create(const tffr_params* p, const double* k, const double* ku,
   g.lognfx = lognx;
   g.lognfy = logny;
   g.W = W;
+  g.literal = lit ? 1 : 0;
+  g.lit_taps = lit ? 2 * (int)p->q : 0;
   g.weighting = p->weighting;
   g.thresh_mode = p->thresh_mode;
   g.band_r = p->band_r;
@@ -603,8 +616,11 @@ tffr_status plan_create(const tffr_params* p, const double* k, const double* ku,
     }
   g.yemax = yemax;
   const HostKx hkx{k, ku, kx_tab, p->n_freq};
-  range_schedule(p, hkx, nfx, tffr::rows_threads(lognx), &g.sub, &g.part_len, &g.range_mode);
+  range_schedule(p, hkx, nfx, lit ? 2 * (int)p->q : W, tffr::rows_threads(lognx), &g.sub, &g.part_len,
+                 &g.range_mode);
   std::vector<double> dx = deapod_table(p->mx, nfx, W, P->beta), dy = deapod_table(p->my, nfy, W, P->beta);
+  if (lit)  // divide by the window w(u) = exp(-a |u|), u = X / fov_x (Algorithm 1)
+    for (int j = 0; j < p->mx; ++j) dx[j] = std::exp(p->window_a * std::fabs((j - p->mx / 2) / (double)p->mx));
   std::vector<double> twx = twiddle_table(nfx), twy = twiddle_table(nfy);
   if (P->dbl()) {
     s = upload(P->ky, kuv);

@@ -22,6 +22,8 @@ struct Geo {
   int32_t n_pulses, n_freq, mx, my;
   int32_t nfx, nfy, lognfx, lognfy;  // fine grid sizes (powers of two)
   int32_t W;                         // gridding kernel width (taps)
+  int32_t literal;                   // range gridding with the window's lattice transform (Algorithm 1)
+  int32_t lit_taps;                  // its taps per sample: 2 q
   int32_t weighting, thresh_mode, band_r, band_b;
   int32_t use_poly, nseg, deg;  // tFFR weight polynomial (float path)
   int32_t sub;                  // range gridding: samples per thread per sub-pass group

@@ -346,6 +346,55 @@ __device__ __forceinline__ R es_shape(const Geo& g) {
   return sizeof(R) == 4 ? (R)(g.beta * 1.4426950408889634) : (R)g.beta;
 }
 
+// Literal Algorithm-1 range gridding (Eq. (8)): a sample at lattice coordinate lam
+// reaches the image-lattice points m with |m - lam| < q, with weight R_W(m - lam), the
+// window's finite-interval transform.  On the M-point lattice row (M = image size) the
+// sample sits at cell + fraction f = frac(tt) M, tt = kx fov_x / (2 pi M) cycles per
+// pixel; the taps are d = k0 + i - f, k0 = floor(f - q) + 1, i < 2q (0 where |d| >= q:
+// a sample on the lattice reaches 2q - 1 points).  One sincos(pi d0) serves every tap,
+// since sin, cos(pi (d0 + i)) = (-1)^i sin, cos(pi d0).  FP64 taps; kept out of line.
+__device__ __forceinline__ double lit_tap(double d, double sgn, double s0, double c0, double a, double ema2) {
+  const double b = 2.0 * TFFR_PI * d;
+  const double den = a * a + b * b;
+  if (den == 0.0) return 1.0;
+  return 2.0 * (a + ema2 * (b * (sgn * s0) - a * (sgn * c0))) / den;
+}
+template <typename R>
+__device__ __attribute__((noinline)) void lit_spread(cplx<R>* buf, int N, double tt, double q, int ntaps, double a,
+                                                     double ema2, cplx<R> c) {
+  const double u = (tt - floor(tt)) * (double)N;
+  const double fu = floor(u), fl = u - fu;
+  const int k0 = (int)floor(fl - q) + 1;
+  const int cell = (int)fu + k0;
+  const double d0 = (double)k0 - fl;
+  double s0, c0;
+  sincospi(d0, &s0, &c0);
+  for (int i = 0; i < ntaps; ++i) {
+    const double d = d0 + (double)i;
+    const R phi = fabs(d) < q ? (R)lit_tap(d, (i & 1) ? -1.0 : 1.0, s0, c0, a, ema2) : (R)0;
+    cplx<R>& bb = buf[(cell + i) & (N - 1)];
+    bb = bb + phi * c;
+  }
+}
+template <typename R>
+__device__ __attribute__((noinline)) cplx<R> lit_gather(const cplx<R>* buf, int N, double tt, double q, int ntaps,
+                                                        double a, double ema2) {
+  const double u = (tt - floor(tt)) * (double)N;
+  const double fu = floor(u), fl = u - fu;
+  const int k0 = (int)floor(fl - q) + 1;
+  const int cell = (int)fu + k0;
+  const double d0 = (double)k0 - fl;
+  double s0, c0;
+  sincospi(d0, &s0, &c0);
+  cplx<R> acc = {0, 0};
+  for (int i = 0; i < ntaps; ++i) {
+    const double d = d0 + (double)i;
+    const R phi = fabs(d) < q ? (R)lit_tap(d, (i & 1) ? -1.0 : 1.0, s0, c0, a, ema2) : (R)0;
+    acc = acc + phi * buf[(cell + i) & (N - 1)];
+  }
+  return acc;
+}
+
 // Fine-grid position of a sample with lattice-per-pixel coordinate t (cycles per pixel):
 // u = frac(t) n in [0, n), split in FP64 into an integer cell and a fraction.
 template <typename R>
@@ -467,16 +516,20 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(Geo g, Tab<R> t, int stype, con
               const double kx = kx_of(t, kr[j], ku);
               const double lam = lattice_coord(kx, g);
               const cplx<R> c = weighted_sample<R>(g, t, poly, stype, samples, w, n, p, ku, lam, rot, sr[j]);
-              int ui;
-              R f;
-              fine_pos<R>(kx * g.tx_scale, N, ui, f);
-              const int k0 = (int)ceil(f - halfw);
-              const int cell = ui + k0;
-              const R z0 = ((R)k0 - f) * inv_halfw;
-              for (int i = 0; i < W; ++i) {
-                const R phi = es_kernel(z0 + (R)i * inv_halfw, beta);
-                cplx<R>& bb = buf[(cell + i) & (N - 1)];
-                bb = bb + phi * c;
+              if (g.literal) {
+                lit_spread<R>(buf, N, kx * g.tx_scale, g.q, g.lit_taps, g.a, g.ema2, c);
+              } else {
+                int ui;
+                R f;
+                fine_pos<R>(kx * g.tx_scale, N, ui, f);
+                const int k0 = (int)ceil(f - halfw);
+                const int cell = ui + k0;
+                const R z0 = ((R)k0 - f) * inv_halfw;
+                for (int i = 0; i < W; ++i) {
+                  const R phi = es_kernel(z0 + (R)i * inv_halfw, beta);
+                  cplx<R>& bb = buf[(cell + i) & (N - 1)];
+                  bb = bb + phi * c;
+                }
               }
             }
             __syncthreads();
@@ -1022,16 +1075,20 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
       if (w && !ffr) w_next = w[base + p_next];
     }
     const double kx = kx_of(t, kp, ku);
-    int ui;
-    R f;
-    fine_pos<R>(kx * g.tx_scale, N, ui, f);
-    const int k0 = (int)ceil(f - halfw);
-    const int cell = ui + k0;
-    const R z0 = ((R)k0 - f) * inv_halfw;
     cplx<R> a = {0, 0};
-    for (int i = 0; i < g.W; ++i) {
-      const R phi = es_kernel(z0 + (R)i * inv_halfw, beta);
-      a = a + phi * buf[(cell + i) & (N - 1)];
+    if (g.literal) {
+      a = lit_gather<R>(buf, N, kx * g.tx_scale, g.q, g.lit_taps, g.a, g.ema2);
+    } else {
+      int ui;
+      R f;
+      fine_pos<R>(kx * g.tx_scale, N, ui, f);
+      const int k0 = (int)ceil(f - halfw);
+      const int cell = ui + k0;
+      const R z0 = ((R)k0 - f) * inv_halfw;
+      for (int i = 0; i < g.W; ++i) {
+        const R phi = es_kernel(z0 + (R)i * inv_halfw, beta);
+        a = a + phi * buf[(cell + i) & (N - 1)];
+      }
     }
     if (ffr) {
       gbuf[p] = a;

@@ -10,8 +10,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (C64, C64_FP16IN, C128, THRESH_CORRELATION, THRESH_LITERAL, W_FFR, W_NONE, W_QUAD,  # noqa: F401
-                   W_TFFR, W_USER, Params)
+from ._lib import (C64, C64_FP16IN, C128, GRID_ES, GRID_LITERAL, THRESH_CORRELATION, THRESH_LITERAL,  # noqa: F401
+                   W_FFR, W_NONE, W_QUAD, W_TFFR, W_USER, Params)
 
 _DT = {C64: (torch.complex64, torch.float32), C128: (torch.complex128, torch.float64),
        C64_FP16IN: (torch.complex64, torch.float32)}
