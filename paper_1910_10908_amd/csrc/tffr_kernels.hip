@@ -696,11 +696,24 @@ __device__ __forceinline__ void load_entries(const Tab<R>& t, int e, CellEntries
   }
 }
 
+// CB consecutive complex values, moved as one wide access where aligned
+template <typename R, int CB>
+struct alignas(CB * sizeof(cplx<R>) >= 16 ? 16 : CB * sizeof(cplx<R>)) CVec {
+  cplx<R> v[CB];
+};
+
 // Stage the block's CB columns of the range spectra in LDS as hs[n][c] (zeros past the
-// last column of the image).
+// last column of the image).  A slice's CB values are one wide load when the block is
+// full and the rows keep CB-alignment.
 template <typename R, int NT, int CB>
 __device__ __forceinline__ void stage_spectra(const Geo& g, const cplx<R>* __restrict__ hx, cplx<R>* hs, int c0,
                                               int ncol) {
+  if (CB > 1 && ncol == CB && g.mx % CB == 0) {
+    for (int nn = threadIdx.x; nn < g.n_pulses; nn += NT)
+      *reinterpret_cast<CVec<R, CB>*>(hs + nn * CB) =
+          *reinterpret_cast<const CVec<R, CB>*>(hx + (size_t)nn * g.mx + c0);
+    return;
+  }
   const int total = g.n_pulses * CB;
   for (int idx = threadIdx.x; idx < total; idx += NT) {
     const int nn = idx / CB, c = idx - nn * CB;
@@ -737,11 +750,14 @@ __device__ __forceinline__ void cols_gather(const Geo& g, const Tab<R>& t, CellE
 }
 
 // Azimuth interpolation (type 2) of NC fine columns buf[c][.] at every slice: the W taps
-// of slice n are loaded once and applied to all NC columns; out[c][n] gets column c.
-template <typename R, int N, int NT, int NC>
+// of slice n are loaded once and applied to all NC columns; column c goes to output
+// array c / CS at image column c0 + c % CS (each array's CS columns as one wide store
+// when the block is full and rows keep CS-alignment).
+template <typename R, int N, int NT, int NC, int CS>
 __device__ __forceinline__ void cols_interp(const Geo& g, const Tab<R>& t, const cplx<R>* buf, int nc_valid,
-                                            cplx<R>* const* out, int c_stride, int c0) {
+                                            cplx<R>* const* out, int c0) {
   const int W = g.W;
+  const bool wide = CS > 1 && nc_valid == CS && g.mx % CS == 0;
   for (int nn = threadIdx.x; nn < g.n_pulses; nn += NT) {
     const int ys = t.ystart[nn];
     const R* tap = t.ytap + (size_t)nn * W;
@@ -754,9 +770,19 @@ __device__ __forceinline__ void cols_interp(const Geo& g, const Tab<R>& t, const
 #pragma unroll
       for (int c = 0; c < NC; ++c) acc[c] = acc[c] + tp * buf[c * N + cell];
     }
+    if (wide) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-      if ((c % c_stride) < nc_valid) out[c / c_stride][(size_t)nn * g.mx + c0 + (c % c_stride)] = acc[c];
+      for (int o = 0; o < NC / CS; ++o) {
+        CVec<R, CS> v;
+#pragma unroll
+        for (int c = 0; c < CS; ++c) v.v[c] = acc[o * CS + c];
+        *reinterpret_cast<CVec<R, CS>*>(out[o] + (size_t)nn * g.mx + c0) = v;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if ((c % CS) < nc_valid) out[c / CS][(size_t)nn * g.mx + c0 + (c % CS)] = acc[c];
+    }
   }
 }
 
@@ -911,7 +937,7 @@ __global__ __launch_bounds__(NT) void k_ent_cols(Geo g, Tab<R> t, const cplx<R>*
   __syncthreads();
   lds_fft<-1, N, NT, 2 * CB>(buf, tw);  // buf and hs are contiguous: 2 CB columns
   cplx<R>* outs[2] = {h2, h1};
-  cols_interp<R, N, NT, 2 * CB>(g, t, buf, ncol, outs, CB, c0);
+  cols_interp<R, N, NT, 2 * CB, CB>(g, t, buf, ncol, outs, c0);
 }
 
 // Image entropy from the per-block sums: E = ln S - (1/S) sum a ln a.  One block.
@@ -990,7 +1016,7 @@ __global__ __launch_bounds__(NT) void k_adj_cols(Geo g, Tab<R> t, const cplx<R>*
   __syncthreads();
   lds_fft<-1, N, NT, CB>(buf, tw);
   cplx<R>* outs[1] = {hx};
-  cols_interp<R, N, NT, CB>(g, t, buf, ncol, outs, CB, c0);
+  cols_interp<R, N, NT, CB, CB>(g, t, buf, ncol, outs, c0);
 }
 
 // Range stage, type 2: per slice, divide by the kernel transform, zero-pad, forward FFT
