@@ -202,6 +202,20 @@ tffr_status tffr_entropy_step(tffr_plan *plan, const void *d_samples, const void
                               double *d_loss, void *d_grad_samples, void *d_grad_phase,
                               void *d_grad_dalong, void *d_work, tffr_stream stream);
 
+/* Gradients with respect to the sample coordinates, for refining the geometry itself
+ * (the method's weights held fixed as constants of the geometry):
+ *   d_grad_image  [mx][my] complex G = dL/dRe I + i dL/dIm I, read only
+ *   d_samples, d_phase, d_dalong, d_user_w as in tffr_forward (d_samples required)
+ *   d_grad_kx     [n_pulses][n_freq] real, written: dL/dkx = Re(i c conj(A^H(X G)))
+ *   d_grad_ky     [n_pulses] real, written: dL/dky_n = sum_p Re(i c conj(A^H(Y G)))
+ * with c the weighted, phased sample and A^H the adjoint sum; X, Y the pixel coordinates
+ * of the image convention (dI/dkx = i X c e^{i(kx X + ky Y)}).  Uses the workspace's two
+ * range-spectra arrays.  TFFR_ERR_UNSUPPORTED when two fine rows / columns do not fit in
+ * LDS (fine grids of 16384 points). */
+tffr_status tffr_coord_grad(tffr_plan *plan, const void *d_grad_image, const void *d_samples,
+                            const void *d_phase, const void *d_dalong, const void *d_user_w,
+                            void *d_grad_kx, void *d_grad_ky, void *d_work, tffr_stream stream);
+
 /* Per-slice phase and position gradients from a sample cotangent computed elsewhere:
  *   d_samples      [n_pulses][n_freq] complex (dtype), the raw samples s
  *   d_grad_samples [n_pulses][n_freq] complex (real type of the plan): dL/dRe s + i dL/dIm s

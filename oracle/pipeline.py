@@ -138,3 +138,27 @@ def backward(prob, grad_image, s, phase=None, dalong=None, user_w=None):
     grad_s = grad_sp * np.conj(rot)
     dpsi = np.sum(np.real(np.conj(grad_sp) * 1j * sp), axis=1)
     return grad_s, dpsi, ky * dpsi
+
+
+def coordinate_gradients(prob, grad_image, s, phase=None, dalong=None, user_w=None):
+    """Gradients of a real loss with respect to the sample coordinates, the method's
+    weights held fixed (they are constants of the geometry in the forward map):
+
+        dI_j / dkx[n,p] = i X_jx c[n,p] exp(i(kx X_jx + ky Y_jy)),  and likewise with Y for ky[n]
+
+    so with dL = Re(sum_j conj(G_j) dI_j), G = grad_image:
+
+        dL/dkx[n,p] = Re(i c[n,p] conj((A^H (X G))[n,p]))
+        dL/dky[n]   = sum_p Re(i c[n,p] conj((A^H (Y G))[n,p]))
+
+    A^H the plain adjoint sum (nudft.adjoint).  Returns (grad_kx [n][p], grad_ky [n]).
+    """
+    kx, ky, lam, X, Y = prob.geometry()
+    c = weighted_samples(prob, s, phase, dalong, user_w)
+    G = np.asarray(grad_image, dtype=np.complex128)
+    aX = nudft.adjoint(X[:, None] * G, kx, ky, X, Y)
+    aY = nudft.adjoint(Y[None, :] * G, kx, ky, X, Y)
+    gkx = np.real(1j * c * np.conj(aX))
+    gky = np.sum(np.real(1j * c * np.conj(aY)), axis=1)
+    return gkx, gky
+

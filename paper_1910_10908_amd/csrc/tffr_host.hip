@@ -141,6 +141,7 @@ struct tffr_plan {
   DevBuf k, ku, kx, ky, ystart, ytap, deapx, deapy, twx, twy, poly, ffr_d, ycn, ycw;
   // workspace layout
   bool ent_fused = false;  // entropy step uses the fused azimuth kernel
+  int coord_cb = 0;        // azimuth block width of the coordinate-gradient kernels (0: unsupported)
   size_t off_hx = 0, off_h2 = 0, off_cblk = 0, off_part = 0, off_stats = 0, off_kept = 0, off_count = 0, off_status = 0, off_gband = 0, off_zband = 0,
          off_dband = 0, work_bytes = 0;
   bool dbl() const { return prm.dtype == TFFR_C128; }
@@ -551,6 +552,10 @@ tffr_status plan_create(const tffr_params* p, const double* k, const double* ku,
   // staged-spectra space, at least [CB][nfy] more
   P->ent_fused = ((size_t)nfy * cb + std::max<size_t>((size_t)p->n_pulses * cb, (size_t)nfy * cb) + twy_n) * csz <=
                  lds_max;
+  // coordinate gradients: two fields per fine row / column in LDS
+  if ((2 * (size_t)nfx + twx_n) * csz + 2048 <= lds_max)
+    for (int c = cb; c >= 1 && !P->coord_cb; c >>= 1)
+      if ((2 * (size_t)nfy * c + twy_n) * csz <= lds_max) P->coord_cb = c;
 
   tffr::Geo& g = P->geo;
   g.n_pulses = p->n_pulses;
@@ -570,6 +575,7 @@ tffr_status plan_create(const tffr_params* p, const double* k, const double* ku,
   g.beta = P->beta;
   g.tx_scale = p->fov_x / (2.0 * kPi * p->mx);
   g.fov_x = p->fov_x;
+  g.fov_y = p->fov_y;
   g.a = p->window_a;
   g.q = p->q;
   g.tau = p->tau;
@@ -793,6 +799,35 @@ tffr_status tffr_entropy_step(tffr_plan* P, const void* smp, const void* ph, con
   hipStream_t st = (hipStream_t)stream;
   return P->dbl() ? do_entropy_step<double>(P, smp, ph, da, uw, img, loss, gs, gph, gda, work, st)
                   : do_entropy_step<float>(P, smp, ph, da, uw, img, loss, gs, gph, gda, work, st);
+}
+
+tffr_status tffr_coord_grad(tffr_plan* P, const void* cot, const void* smp, const void* ph, const void* da,
+                            const void* uw, void* gkx, void* gky, void* work, tffr_stream stream) {
+  if (!P || !cot || !smp || !gkx || !gky || !work) return TFFR_ERR_ARG;
+  if (P->prm.weighting == TFFR_W_USER && !uw) return TFFR_ERR_ARG;
+  if (!aligned(work, 16) || !aligned(cot, P->csize() / 2) || !aligned(smp, 4) || !aligned(gkx, P->rsize()) ||
+      !aligned(gky, P->rsize()))
+    return TFFR_ERR_LAYOUT;
+  if (!P->coord_cb) return TFFR_ERR_UNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  char* wb = (char*)work;
+  hipError_t e;
+  if (P->dbl()) {
+    const double* w = (const double*)uw;
+    if (!w && P->prm.weighting == TFFR_W_FFR) w = (const double*)P->ffr_d.p;
+    e = tffr::launch_coord_grad<double>(P->geo, tables<double>(P), P->coord_cb, sample_type(P),
+                                        (const cplx<double>*)cot, smp, (const double*)ph, (const double*)da, w,
+                                        (cplx<double>*)(wb + P->off_hx), (cplx<double>*)(wb + P->off_h2),
+                                        (double*)gkx, (double*)gky, st);
+  } else {
+    const float* w = (const float*)uw;
+    if (!w && P->prm.weighting == TFFR_W_FFR) w = (const float*)P->ffr_d.p;
+    e = tffr::launch_coord_grad<float>(P->geo, tables<float>(P), P->coord_cb, sample_type(P),
+                                       (const cplx<float>*)cot, smp, (const float*)ph, (const float*)da, w,
+                                       (cplx<float>*)(wb + P->off_hx), (cplx<float>*)(wb + P->off_h2),
+                                       (float*)gkx, (float*)gky, st);
+  }
+  return hip_status(e);
 }
 
 tffr_status tffr_row_phase_grad(tffr_plan* P, const void* smp, const void* gs, void* gph, void* gda,

@@ -34,6 +34,7 @@ struct Geo {
   double beta;                  // ES kernel shape
   double tx_scale;              // kx -> cycles per range pixel: fov_x / (2 pi mx)
   double fov_x;                 // kx -> lattice coordinate: kx * fov_x / (2 pi)
+  double fov_y;                 // azimuth scene extent (pixel coordinates Y)
   double a, q, tau;
   double ema2, epa2;  // exp(-a/2), exp(+a/2)
   double inv_g0;      // 1/g(0) for a sample exactly on the lattice
@@ -98,6 +99,10 @@ hipError_t launch_adj_rows(const Geo& g, const Tab<R>& t, int stype, const cplx<
                            const void* samples, const R* phase, const R* dalong, const R* w,
                            cplx<R>* grad_s, R* grad_phase, R* grad_dalong, const EntComb<R>& ec,
                            hipStream_t st);
+template <typename R>
+hipError_t launch_coord_grad(const Geo& g, const Tab<R>& t, int cb, int stype, const cplx<R>* cot,
+                             const void* samples, const R* phase, const R* dalong, const R* w, cplx<R>* h0,
+                             cplx<R>* h1, R* grad_kx, R* grad_ky, hipStream_t st);
 template <typename R>
 hipError_t launch_row_phase_grad(const Geo& g, const Tab<R>& t, int stype, const void* samples,
                                  const cplx<R>* grad_s, R* grad_phase, R* grad_dalong, hipStream_t st);

@@ -161,6 +161,20 @@ class Plan:
                                          _stream()), "tffr_adjoint")
         return out, gph, gda
 
+    def tffr_coord_grad(self, grad_image, samples, phase=None, dalong=None, user_w=None):
+        """(dL/dkx [n_pulses][n_freq], dL/dky [n_pulses]) for a cotangent of the image."""
+        self._chk(grad_image, self.shape_image, self.ctype, "grad_image")
+        self._chk_samples(samples)
+        self._chk(phase, (self.params.n_pulses,), self.rtype, "phase")
+        self._chk(dalong, (self.params.n_pulses,), self.rtype, "dalong")
+        self._chk_weights(user_w)
+        gkx = torch.empty(self.shape_samples, dtype=self.rtype, device=self.device)
+        gky = torch.empty(self.params.n_pulses, dtype=self.rtype, device=self.device)
+        _lib.check(self.lib.tffr_coord_grad(self.handle, _ptr(grad_image), _ptr(samples), _ptr(phase), _ptr(dalong),
+                                            _ptr(user_w), _ptr(gkx), _ptr(gky), _ptr(self.work), _stream()),
+                   "tffr_coord_grad")
+        return gkx, gky
+
     def tffr_row_phase_grad(self, samples, grad_samples, want_dalong=True):
         """Per-slice (dL/dphi, dL/d du) from a sample cotangent computed elsewhere."""
         self._chk_samples(samples)

@@ -506,3 +506,27 @@ def test_literal_gridding_adjoint_identity(dtype, width):
     rhs = np.vdot(Ahy, sr)
     tol = 1e-5 if dtype == T.C64 else 1e-11
     assert abs(lhs - rhs) <= tol * abs(lhs)
+
+
+# ---------------------------------------------------------------- coordinate gradients
+@pytest.mark.parametrize("dtype,width", [(T.C64, 7), (T.C128, 14)])
+@pytest.mark.parametrize("weighting", [T.W_TFFR, T.W_QUAD, T.W_FFR])
+def test_coordinate_gradients_vs_oracle(dtype, width, weighting):
+    """tffr_coord_grad: dL/dkx per sample and dL/dky per slice for an image cotangent,
+    weights held fixed, against the oracle's adjoint sums of the X- and Y-weighted
+    cotangent."""
+    print(f"coordinate gradients dtype={dtype} weighting={weighting}", flush=True)
+    case = Case(12, 100, 64, my=48, fov=40.0, fov_y=30.0, weighting=weighting, dtype=dtype, width=width, seed=61)
+    s, st = case.samples()
+    phase = case.rng.normal(0, 0.5, 12)
+    dal = case.rng.normal(0, 0.004, 12)
+    G = case.rng.standard_normal((64, 48)) + 1j * case.rng.standard_normal((64, 48))
+    Gt = torch.as_tensor(G, dtype=case.ctype, device=DEV)
+    gkx, gky = case.plan.tffr_coord_grad(Gt, st, case.real(phase), case.real(dal))
+    rkx, rky = OP.coordinate_gradients(case.prob, Gt.cpu().numpy().astype(np.complex128), s, case.rounded(phase),
+                                       case.rounded(dal))
+    e1 = rel_l2(gkx.cpu().numpy(), rkx)
+    e2 = np.max(np.abs(gky.cpu().numpy() - rky)) / np.max(np.abs(rky))
+    print(f"  dL/dkx rel-L2 {e1:.3e}  dL/dky {e2:.3e}", flush=True)
+    tol = tol_for(case)
+    assert e1 < 2 * tol and e2 < 20 * tol

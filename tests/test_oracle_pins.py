@@ -569,3 +569,38 @@ def test_literal_vectorised_matches_loops():
                     if abs(m - lam[n, p]) < q:
                         acc += c[n, p] * window.r_w(m - lam[n, p], a) * np.exp(2j * np.pi * m * u)
             assert abs(got[n, j] - np.exp(a * abs(u)) * acc) < 1e-12 * max(1.0, abs(acc))
+
+
+def test_coordinate_gradients_central_differences():
+    """Coordinate gradients of L = sum Re(conj(G) I) (linear in I, so grad_image = G) against
+    central differences of the forward sum under perturbed explicit coordinates, the
+    weights held fixed (user weights)."""
+    rng = np.random.default_rng(44)
+    base = _tiny_problem(5, 9, 12)
+    kx, ky, lam, X, Y = base.geometry()
+    w = rng.uniform(0.5, 1.5, kx.shape)
+    s = rng.standard_normal(kx.shape) + 1j * rng.standard_normal(kx.shape)
+    G = rng.standard_normal((12, 12)) + 1j * rng.standard_normal((12, 12))
+    phase = rng.normal(0, 0.5, 5)
+
+    def prob_at(kxv, kyv):
+        return pipeline.Problem(k=None, ku=None, mx=12, my=12, fov_x=40.0, fov_y=40.0,
+                                weighting=pipeline.WEIGHT_USER, kx_explicit=kxv, ky_explicit=kyv)
+
+    def loss(kxv, kyv):
+        return float(np.sum(np.real(np.conj(G) * pipeline.image(prob_at(kxv, kyv), s, phase, user_w=w))))
+
+    gkx, gky = pipeline.coordinate_gradients(prob_at(kx, ky), G, s, phase, user_w=w)
+    h = 1e-6
+    for (n, p) in [(0, 0), (2, 4), (4, 8)]:
+        kp, km = kx.copy(), kx.copy()
+        kp[n, p] += h
+        km[n, p] -= h
+        fd = (loss(kp, ky) - loss(km, ky)) / (2 * h)
+        assert abs(fd - gkx[n, p]) <= 1e-5 * max(1.0, abs(fd))
+    for n in [0, 3]:
+        yp, ym = ky.copy(), ky.copy()
+        yp[n] += h
+        ym[n] -= h
+        fd = (loss(kx, yp) - loss(kx, ym)) / (2 * h)
+        assert abs(fd - gky[n]) <= 1e-5 * max(1.0, abs(fd))
