@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the plain FFR / NUFFT steps")
     ap.add_argument("--cpu-cols", type=int, default=48, help="image columns in the CPU oracle sample")
+    ap.add_argument("--sweep", action="store_true",
+                    help="one JSON line per workload: tFFR step, plain NUFFT and plain FFR (where the frame "
+                         "product is invertible), accuracy vs the oracle, peak memory, oracle timing")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many eager steps of the tFFR path (for profilers) and exit")
     return ap.parse_args()
@@ -159,12 +162,73 @@ def cpu_baseline(wl, k, ku, s, phase, dalong, cols):
     }, img_cols, col_idx
 
 
+def sweep(args):
+    """Every workload at its own size and precision: the tFFR entropy step, the plain-NUFFT
+    (quadrature) step and the plain-FFR step (weights solved inside the step), each timed
+    as the faster of graph replay and eager launches; accuracy of the tFFR image against
+    the FP64 oracle on sampled columns; peak device memory of one tFFR step; the oracle's
+    own time for the step on the host (bounded sample, extrapolated)."""
+    import torch
+
+    from paper_1910_10908_amd import scenes
+    from paper_1910_10908_amd import tffr as T
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    for name in scenes.WORKLOAD_ORDER:
+        wl = scenes.WORKLOADS[name]
+        dtype = T.C128 if wl.dtype == "c128" else T.C64
+        ctype, rtype = (torch.complex128, torch.float64) if dtype == T.C128 else (torch.complex64, torch.float32)
+        inp = scenes.make_inputs(wl, device=dev, scene=True)
+        k, ku = inp["k"], inp["ku"]
+        s = inp["samples"].to(ctype).contiguous()
+        ph = torch.zeros(wl.n_pulses, dtype=rtype, device=dev)
+        da = torch.zeros_like(ph)
+        steps = max(10, min(200, int(4e8 / wl.n_samples)))
+        rec = {"workload": name, "n_pulses": wl.n_pulses, "n_freq": wl.n_freq, "image": [wl.m, wl.m],
+               "dtype": wl.dtype, "kernel_width": wl.kernel_width, "steps": steps}
+        for label, wt in (("tffr", T.W_TFFR), ("plain_nufft_quad", T.W_QUAD), ("plain_ffr", T.W_FFR)):
+            prm = T.default_params(n_pulses=wl.n_pulses, n_freq=wl.n_freq, mx=wl.m, my=wl.m, fov_x=wl.fov,
+                                   fov_y=wl.fov, weighting=wt, kernel_width=wl.kernel_width, dtype=dtype)
+            try:
+                plan = T.Plan(prm, k, ku, dev)
+            except RuntimeError as e:
+                rec[label] = {"error": str(e)}
+                continue
+            st = Step(T, plan, s, ph, da, ffr=(wt == T.W_FFR))
+            ms_e, _ = time_step(torch, st, steps, 5, graph=False)
+            ms_g, _ = time_step(torch, st, steps, 5, graph=True)
+            ms = min(ms_e, ms_g)
+            rec[label] = {"ms_per_step": ms, "Msamples_per_s": wl.n_samples / (ms * 1e-3) / 1e6,
+                          "timing": "hip_graph" if ms_g < ms_e else "eager"}
+            if wt == T.W_TFFR:
+                rec[label]["range_kernel"] = "k_fwd_rows_run" if plan.range_mode == 1 else "k_fwd_rows"
+                torch.cuda.synchronize()
+                torch.cuda.reset_peak_memory_stats()
+                st()
+                torch.cuda.synchronize()
+                rec[label]["peak_device_MiB"] = torch.cuda.max_memory_allocated() / 2 ** 20
+                img = st.img.cpu().numpy().astype(np.complex128)
+            del plan, st
+        cols = max(2, min(48, int(48 * 524288 / wl.n_samples)))
+        base, ref_cols, col_idx = cpu_baseline(wl, k, ku, s.cpu().numpy().astype(np.complex128),
+                                               np.zeros(wl.n_pulses), np.zeros(wl.n_pulses), cols)
+        rec["accuracy"] = {"rel_l2_vs_fp64": float(np.linalg.norm(img[col_idx] - ref_cols) /
+                                                   np.linalg.norm(ref_cols)),
+                           "sample": f"{len(col_idx)} of {wl.m} image columns"}
+        rec["cpu_oracle"] = base
+        print(json.dumps(rec), flush=True)
+        del inp, s, img
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU slab design is described but not "
               "built, so --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    if args.sweep:
+        return sweep(args)
     import torch
 
     from paper_1910_10908_amd import scenes
