@@ -231,33 +231,31 @@ __device__ __forceinline__ double kx_of(const Tab<R>& t, double raw, double ku) 
   return t.kx ? raw : stolt_kx(raw, ku);
 }
 
-// Finite-interval cosine transforms of w = exp(-a|t|) and 1/w over [-1/2, 1/2]
-// (the entries of W and Psi on the image's own lattice); ema2 = exp(-a/2), epa2 = exp(a/2).
-__device__ __forceinline__ double r_w(double d, double a, double ema2) {
-  const double b = 2.0 * TFFR_PI * d;
-  double sn, cs;
-  sincos(b / 2.0, &sn, &cs);
-  const double den = a * a + b * b;
-  if (den == 0.0) return 1.0;
-  return 2.0 * (a + ema2 * (b * sn - a * cs)) / den;
-}
-__device__ __forceinline__ double r_psi(double d, double a, double epa2) {
-  const double b = 2.0 * TFFR_PI * d;
-  double sn, cs;
-  sincos(b / 2.0, &sn, &cs);
-  const double den = a * a + b * b;
-  if (den == 0.0) return 1.0;
-  return 2.0 * (epa2 * (b * sn + a * cs) - a) / den;
-}
-
 // g(delta) = sum_{|k - delta| < q} R_Psi(k - delta) R_W(k - delta): the diagonal of the
-// truncated frame product for a sample at fractional lattice offset delta.
+// truncated frame product for a sample at fractional lattice offset delta.  R_W and R_Psi
+// are the finite-interval cosine transforms of w = exp(-a|t|) and 1/w over [-1/2, 1/2]
+// (the entries of W and Psi on the image's own lattice), with b = 2 pi d:
+//   R_W(d) = 2 (a + e^{-a/2} (b sin(b/2) - a cos(b/2))) / (a^2 + b^2),
+//   R_Psi(d) = 2 (e^{a/2} (b sin(b/2) + a cos(b/2)) - a) / (a^2 + b^2);
+// ema2 = exp(-a/2), epa2 = exp(a/2).  Every tap
+// has b/2 = pi (k - delta), so one sincos(pi delta) serves them all:
+// sin(pi (k - delta)) = -(-1)^k sin(pi delta), cos(pi (k - delta)) = (-1)^k cos(pi delta).
 __device__ double frame_diag(double delta, double a, double q, double ema2, double epa2) {
   const int K = (int)ceil(q) + 1;
+  double sd, cd;
+  sincospi(delta, &sd, &cd);
   double acc = 0.0;
   for (int k = -K; k <= K; ++k) {
     const double d = (double)k - delta;
-    if (fabs(d) < q) acc += r_psi(d, a, epa2) * r_w(d, a, ema2);
+    if (fabs(d) < q) {
+      const double sg = (k & 1) ? -1.0 : 1.0;
+      const double sn = -sg * sd, cs = sg * cd;
+      const double b = 2.0 * TFFR_PI * d;
+      const double den = a * a + b * b;
+      const double rw = den == 0.0 ? 1.0 : 2.0 * (a + ema2 * (b * sn - a * cs)) / den;
+      const double rp = den == 0.0 ? 1.0 : 2.0 * (epa2 * (b * sn + a * cs) - a) / den;
+      acc += rp * rw;
+    }
   }
   return acc;
 }
