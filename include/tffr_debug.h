@@ -15,9 +15,10 @@ extern "C" {
 
 /* `batch` in-LDS FFTs of length 2^log2n (6 <= log2n <= 14), the transform used by the
  * 2-D inverse FFT of Algorithm 1: out[b][j] = sum_g in[b][g] exp(sign 2 pi i g j / n),
- * sign = +1 or -1, no scaling.  in/out: device complex (dtype TFFR_C64 or TFFR_C128),
- * [batch][n]; in-place allowed. */
-tffr_status tffr_debug_fft(int32_t log2n, int32_t batch, int32_t sign, int32_t dtype,
+ * sign = +1 or -1, no scaling.  max_radix 8 or 16: the Stockham stages' radix (the
+ * dense-slice range kernel uses 16, every other kernel 8).  in/out: device complex
+ * (dtype TFFR_C64 or TFFR_C128), [batch][n]; in-place allowed.  Synchronises. */
+tffr_status tffr_debug_fft(int32_t log2n, int32_t batch, int32_t sign, int32_t max_radix, int32_t dtype,
                            const void *d_in, void *d_out, tffr_stream stream);
 
 /* Range stage of the forward path for every slice.  stage 0: the gridded fine rows

@@ -62,7 +62,8 @@ _PROTOS = {
     "tffr_row_phase_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "tffr_coord_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tffr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
-    "tffr_debug_fft": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp]),
+    "tffr_debug_fft": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                      _vp, _vp, _vp]),
     "tffr_debug_rows": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tffr_debug_cols": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "tffr_debug_ent_cols": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),

@@ -882,9 +882,10 @@ tffr_status tffr_kept_count(tffr_plan* P, void* work, int64_t* count, tffr_strea
   return TFFR_OK;
 }
 
-tffr_status tffr_debug_fft(int32_t log2n, int32_t batch, int32_t sign, int32_t dtype, const void* in, void* out,
-                           tffr_stream stream) {
+tffr_status tffr_debug_fft(int32_t log2n, int32_t batch, int32_t sign, int32_t max_radix, int32_t dtype,
+                           const void* in, void* out, tffr_stream stream) {
   if (log2n < 6 || log2n > kMaxLogN || batch < 1 || (sign != 1 && sign != -1) || !in || !out) return TFFR_ERR_ARG;
+  if (max_radix != 8 && max_radix != 16) return TFFR_ERR_ARG;
   if (dtype != TFFR_C64 && dtype != TFFR_C128) return TFFR_ERR_UNSUPPORTED;
   const size_t csz = dtype == TFFR_C128 ? 16 : 8;
   if (csz * (((size_t)1 << log2n) + ((size_t)1 << log2n) / 64 + 64) > tffr::max_dynamic_lds())
@@ -896,9 +897,9 @@ tffr_status tffr_debug_fft(int32_t log2n, int32_t batch, int32_t sign, int32_t d
   tffr_status s = dtype == TFFR_C128 ? upload(dtw, tw) : upload(dtw, cast<float>(tw));
   if (s != TFFR_OK) return s;
   hipError_t e = dtype == TFFR_C128
-                     ? tffr::launch_fft<double>(log2n, batch, sign, (const cplx<double>*)in, (cplx<double>*)out,
+                     ? tffr::launch_fft<double>(log2n, batch, sign, max_radix, (const cplx<double>*)in, (cplx<double>*)out,
                                                 (const cplx<double>*)dtw.p, st)
-                     : tffr::launch_fft<float>(log2n, batch, sign, (const cplx<float>*)in, (cplx<float>*)out,
+                     : tffr::launch_fft<float>(log2n, batch, sign, max_radix, (const cplx<float>*)in, (cplx<float>*)out,
                                                (const cplx<float>*)dtw.p, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);  // the twiddle table is freed on return
   return hip_status(e);

@@ -117,7 +117,7 @@ template <typename R>
 hipError_t launch_entropy(const Geo& g, const cplx<R>* img, double* partials, int nparts,
                           double* loss, cplx<R>* grad, hipStream_t st);
 template <typename R>
-hipError_t launch_fft(int log2n, int batch, int sign, const cplx<R>* in, cplx<R>* out,
+hipError_t launch_fft(int log2n, int batch, int sign, int max_radix, const cplx<R>* in, cplx<R>* out,
                       const cplx<R>* tw, hipStream_t st);
 
 size_t max_dynamic_lds();  // bytes of LDS one workgroup may use on this device

@@ -9,7 +9,7 @@
 //
 // Each stage is a 1-D type-1 NUFFT done entirely in LDS: spread with an
 // exponential-of-semicircle (ES) kernel onto an oversampled periodic grid, Stockham
-// radix-8 FFT, keep the centred bins and divide by the kernel's transform.  The
+// radix-16 FFT, keep the centred bins and divide by the kernel's transform.  The
 // adjoint runs the two type-2 stages in reverse.  Samples are read once, each
 // intermediate is written once and read once, and nothing is done with global atomics.
 //
@@ -113,9 +113,50 @@ __device__ __forceinline__ void dft8(cplx<R>* a) {
   a[3] = e[3] + o3;
   a[7] = e[3] - o3;
 }
+// 16-point DFT as 4 x 4: four 4-point DFTs over r = r1 + 4 r2 (stride 4), twiddles
+// exp(SIGN 2 pi i r1 k2 / 16), four 4-point DFTs over r1; output index k2 + 4 k1.
+template <int SIGN, typename R>
+__device__ __forceinline__ void dft16(cplx<R>* a) {
+  cplx<R> t[16];
+#pragma unroll
+  for (int r1 = 0; r1 < 4; ++r1) {
+    cplx<R> u[4] = {a[r1], a[r1 + 4], a[r1 + 8], a[r1 + 12]};
+    dft4<SIGN>(u);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) t[r1 * 4 + k2] = u[k2];
+  }
+  const R c1 = R(0.92387953251128675613), s1 = R(0.38268343236508977173), h = R(0.70710678118654752440);
+  // exp(SIGN 2 pi i m / 16) for m = r1 k2 in {1, 2, 3, 4, 6, 9}
+  auto rot = [&](cplx<R> v, int m) -> cplx<R> {
+    R cr, ci;
+    switch (m) {
+      case 1: cr = c1; ci = s1; break;
+      case 2: cr = h; ci = h; break;
+      case 3: cr = s1; ci = c1; break;
+      case 4: cr = 0; ci = 1; break;
+      case 6: cr = -h; ci = h; break;
+      default: cr = -c1; ci = -s1; break;  // m = 9
+    }
+    ci = R(SIGN) * ci;
+    return {v.x * cr - v.y * ci, v.x * ci + v.y * cr};
+  };
+#pragma unroll
+  for (int r1 = 1; r1 < 4; ++r1)
+#pragma unroll
+    for (int k2 = 1; k2 < 4; ++k2) t[r1 * 4 + k2] = rot(t[r1 * 4 + k2], r1 * k2);
+#pragma unroll
+  for (int k2 = 0; k2 < 4; ++k2) {
+    cplx<R> u[4] = {t[k2], t[4 + k2], t[8 + k2], t[12 + k2]};
+    dft4<SIGN>(u);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) a[k2 + 4 * k1] = u[k1];
+  }
+}
+
 template <int SIGN, int RAD, typename R>
 __device__ __forceinline__ void dft(cplx<R>* a) {
-  if constexpr (RAD == 8) dft8<SIGN>(a);
+  if constexpr (RAD == 16) dft16<SIGN>(a);
+  else if constexpr (RAD == 8) dft8<SIGN>(a);
   else if constexpr (RAD == 4) dft4<SIGN>(a);
   else dft2<SIGN>(a);
 }
@@ -165,7 +206,7 @@ __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* tw) {
       const int k = i & (P - 1);
       if constexpr (P > 1) {
         // one table lookup w = exp(SIGN 2 pi i k / (P RAD)); the other powers by
-        // products of depth <= 3 (w^2 = w w, w^3 = w^2 w, w^4 = w^2 w^2, ...)
+        // short product chains (w^2 = w w, w^3 = w^2 w, w^4 = w^2 w^2, w^r = w^(r-4) w^4)
         constexpr int STEP = N / (P * RAD);
         cplx<R> wp[RAD];
         wp[1] = twiddle<N>(tw, k * STEP);
@@ -174,11 +215,15 @@ __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* tw) {
           wp[2] = cmul(wp[1], wp[1]);
           wp[3] = cmul(wp[2], wp[1]);
         }
-        if constexpr (RAD == 8) {
+        if constexpr (RAD >= 8) {
           wp[4] = cmul(wp[2], wp[2]);
           wp[5] = cmul(wp[4], wp[1]);
           wp[6] = cmul(wp[3], wp[3]);
           wp[7] = cmul(wp[4], wp[3]);
+        }
+        if constexpr (RAD == 16) {
+#pragma unroll
+          for (int r = 8; r < 16; ++r) wp[r] = cmul(wp[r - 4], wp[4]);
         }
 #pragma unroll
         for (int r = 1; r < RAD; ++r) v[b][r] = cmul(v[b][r], wp[r]);
@@ -193,21 +238,24 @@ __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* tw) {
   __syncthreads();
 }
 
-template <int SIGN, int N, int P, int NT, int NBAT, typename R>
+template <int SIGN, int N, int P, int NT, int NBAT, int MAXRAD, typename R>
 __device__ __forceinline__ void fft_from(cplx<R>* buf, const cplx<R>* tw) {
   if constexpr (P < N) {
-    constexpr int RAD = (N / P) >= 8 ? 8 : (N / P);
+    constexpr int RAD = (N / P) >= MAXRAD ? MAXRAD : (N / P);
     fft_stage<SIGN, N, RAD, P, NT, NBAT>(buf, tw);
-    fft_from<SIGN, N, P * RAD, NT, NBAT>(buf, tw);
+    fft_from<SIGN, N, P * RAD, NT, NBAT, MAXRAD>(buf, tw);
   }
 }
 
 // out[j] = sum_g buf[g] exp(SIGN 2 pi i g j / N) for NBAT transforms stored back to back
 // in LDS, in place, natural order; tw is the LDS twiddle table.  Call with all NT
 // threads after a barrier.
-template <int SIGN, int N, int NT, int NBAT = 1, typename R>
+// Stages of radix MAXRAD (8 or 16) and one smaller last stage.  Radix 16 takes fewer LDS
+// passes and, in the dense-slice range kernel, fewer registers (more workgroups per CU);
+// radix 8 keeps more threads busy per stage where a workgroup has few butterflies.
+template <int SIGN, int N, int NT, int NBAT = 1, int MAXRAD = 8, typename R>
 __device__ __forceinline__ void lds_fft(cplx<R>* buf, const cplx<R>* tw) {
-  fft_from<SIGN, N, 1, NT, NBAT>(buf, tw);
+  fft_from<SIGN, N, 1, NT, NBAT, MAXRAD>(buf, tw);
 }
 
 // ----------------------------------------------------------------------------- geometry
@@ -667,7 +715,7 @@ __global__ __launch_bounds__(NT) void k_fwd_rows_run(Geo g, Tab<R> t, int stype,
     const int jx = threadIdx.x + j * NT;
     dx[j] = jx < mx ? t.deapx[jx] : (R)0;
   }
-  lds_fft<+1, N, NT>(buf, tw);
+  lds_fft<+1, N, NT, 1, 16>(buf, tw);
 #pragma unroll
   for (int j = 0; j < DPT; ++j) {
     const int jx = threadIdx.x + j * NT;
@@ -1524,7 +1572,7 @@ __global__ __launch_bounds__(NT) void k_entropy_finish(const cplx<R>* __restrict
 }
 
 // ============================================================================ debug FFT
-template <typename R, int SIGN, int LOGN, int NT>
+template <typename R, int SIGN, int LOGN, int NT, int MAXRAD>
 __global__ __launch_bounds__(NT) void k_fft(const cplx<R>* __restrict__ in, cplx<R>* out, const cplx<R>* __restrict__ tw) {
   constexpr int N = 1 << LOGN;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1534,7 +1582,7 @@ __global__ __launch_bounds__(NT) void k_fft(const cplx<R>* __restrict__ in, cplx
   load_twiddles<N, NT>(twl, tw);
   for (int i = threadIdx.x; i < N; i += NT) buf[i] = in[off + i];
   __syncthreads();
-  lds_fft<SIGN, N, NT>(buf, twl);
+  lds_fft<SIGN, N, NT, 1, MAXRAD>(buf, twl);
   for (int i = threadIdx.x; i < N; i += NT) out[off + i] = buf[i];
 }
 
@@ -1824,22 +1872,16 @@ hipError_t launch_entropy(const Geo& g, const cplx<R>* img, double* partials, in
 }
 
 template <typename R>
-hipError_t launch_fft(int log2n, int batch, int sign, const cplx<R>* in, cplx<R>* out, const cplx<R>* tw,
-                      hipStream_t st) {
+hipError_t launch_fft(int log2n, int batch, int sign, int max_radix, const cplx<R>* in, cplx<R>* out,
+                      const cplx<R>* tw, hipStream_t st) {
   const size_t lds = sizeof(cplx<R>) * (((size_t)1 << log2n) + ((size_t)1 << log2n) / 64 + 64);
   TFFR_LOGN_DISPATCH(log2n, {
     constexpr int NT = nt_for<L>();
-    if (sign > 0) {
-      auto fn = k_fft<R, +1, L, NT>;
-      hipError_t e = allow_lds((const void*)fn, lds);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(fn, dim3(batch), dim3(NT), lds, st, in, out, tw);
-    } else {
-      auto fn = k_fft<R, -1, L, NT>;
-      hipError_t e = allow_lds((const void*)fn, lds);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(fn, dim3(batch), dim3(NT), lds, st, in, out, tw);
-    }
+    auto fn = sign > 0 ? (max_radix == 16 ? k_fft<R, +1, L, NT, 16> : k_fft<R, +1, L, NT, 8>)
+                       : (max_radix == 16 ? k_fft<R, -1, L, NT, 16> : k_fft<R, -1, L, NT, 8>);
+    hipError_t e = allow_lds((const void*)fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3(batch), dim3(NT), lds, st, in, out, tw);
     return hipGetLastError();
   })
 }
@@ -1863,7 +1905,7 @@ hipError_t launch_fft(int log2n, int batch, int sign, const cplx<R>* in, cplx<R>
   template hipError_t launch_ffr<R>(const Geo&, const Tab<R>&, double*, R*, int*, hipStream_t);                \
   template hipError_t launch_entropy<R>(const Geo&, const cplx<R>*, double*, int, double*, cplx<R>*,          \
                                         hipStream_t);                                                          \
-  template hipError_t launch_fft<R>(int, int, int, const cplx<R>*, cplx<R>*, const cplx<R>*, hipStream_t);
+  template hipError_t launch_fft<R>(int, int, int, int, const cplx<R>*, cplx<R>*, const cplx<R>*, hipStream_t);
 
 TFFR_INSTANTIATE(float)
 TFFR_INSTANTIATE(double)

@@ -264,7 +264,7 @@ def tffr_debug_ent_cols(plan, hx):
     return img, h1, h2
 
 
-def tffr_debug_fft(x, sign):
+def tffr_debug_fft(x, sign, max_radix=8):
     """Batched LDS FFT of the rows of x (complex64/complex128, power-of-two length)."""
     lib = _lib.load()
     x = x.contiguous()
@@ -272,7 +272,7 @@ def tffr_debug_fft(x, sign):
     log2n = int(round(np.log2(n)))
     dtype = C128 if x.dtype == torch.complex128 else C64
     out = torch.empty_like(x)
-    _lib.check(lib.tffr_debug_fft(log2n, x.numel() // n, sign, dtype, _ptr(x), _ptr(out), _stream()),
+    _lib.check(lib.tffr_debug_fft(log2n, x.numel() // n, sign, max_radix, dtype, _ptr(x), _ptr(out), _stream()),
                "tffr_debug_fft")
     return out
 
@@ -321,6 +321,31 @@ class _Entropy(torch.autograd.Function):
     def backward(ctx, g):
         (grad,) = ctx.saved_tensors
         return None, grad * g.to(grad.real.dtype)
+
+
+class TFFR:
+    """The plan's forward map as a differentiable operator:
+    TFFR(plan).apply(samples, phase, dalong) -> image; backward is the adjoint (sample,
+    per-pulse phase and along-track position gradients), and TFFRAdjoint(plan) is its
+    transpose.  Tensors must be contiguous on the plan's device (phase / dalong may be
+    None)."""
+
+    def __init__(self, plan, user_w=None):
+        self.plan, self.user_w = plan, user_w
+
+    def apply(self, samples, phase=None, dalong=None):
+        return _Forward.apply(self.plan, samples, phase, dalong, self.user_w)
+
+
+class TFFRAdjoint:
+    """TFFRAdjoint(plan).apply(image) -> samples: the adjoint operator, differentiable (its
+    backward is the forward map)."""
+
+    def __init__(self, plan, user_w=None):
+        self.plan, self.user_w = plan, user_w
+
+    def apply(self, image):
+        return _Adjoint.apply(self.plan, image, self.user_w)
 
 
 def tffr_image(plan, samples, phase=None, dalong=None, user_w=None):
