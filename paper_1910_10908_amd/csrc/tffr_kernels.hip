@@ -1747,11 +1747,15 @@ hipError_t launch_adj_rows(const Geo& g, const Tab<R>& t, int stype, const cplx<
   if (g.weighting == 2) lds += sizeof(cplx<R>) * (size_t)g.n_freq;
   TFFR_LOGN_DISPATCH(g.lognfx, {
     constexpr int NT = nt_for<L>();
-    auto fn = k_adj_rows<R, L, NT>;
+    // short slices on a 2048-point row: twice the threads shorten the per-sample gather
+    // (at most two samples per thread); longer slices keep the FFT's thread count
+    constexpr int NT2 = L == 11 ? 512 : NT;
+    const bool wide = NT2 != NT && g.n_freq <= 2 * NT2;
+    auto fn = wide ? k_adj_rows<R, L, NT2> : k_adj_rows<R, L, NT>;
     hipError_t e = allow_lds((const void*)fn, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn, dim3(g.n_pulses), dim3(NT), lds, st, g, t, stype, hx, samples, phase, dalong, w,
-                       grad_s, grad_phase, grad_dalong, ec);
+    hipLaunchKernelGGL(fn, dim3(g.n_pulses), dim3(wide ? NT2 : NT), lds, st, g, t, stype, hx, samples, phase, dalong,
+                       w, grad_s, grad_phase, grad_dalong, ec);
     return hipGetLastError();
   })
 }
