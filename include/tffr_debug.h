@@ -51,6 +51,16 @@ tffr_status tffr_debug_plan_config(const tffr_plan *plan, int32_t *range_mode, i
 tffr_status tffr_debug_ent_cols(tffr_plan *plan, void *d_hx, void *d_image, void *d_h2,
                                 void *d_work, tffr_stream stream);
 
+/* Range adjoint of the fused entropy step alone (the last launch inside
+ * tffr_entropy_step), on the gradient fields, entropy partial sums and centring constants
+ * that the last tffr_entropy_step or tffr_debug_ent_cols call left in d_work; outputs as
+ * tffr_entropy_step (d_loss receives E).  Reads the workspace only, so repeated calls
+ * give the same result.  TFFR_ERR_UNSUPPORTED when the plan's entropy step is not fused. */
+tffr_status tffr_debug_ent_adj_rows(tffr_plan *plan, const void *d_samples, const void *d_phase,
+                                    const void *d_dalong, const void *d_user_w, double *d_loss,
+                                    void *d_grad_samples, void *d_grad_phase, void *d_grad_dalong,
+                                    void *d_work, tffr_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

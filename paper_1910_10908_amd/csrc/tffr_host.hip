@@ -324,6 +324,27 @@ tffr_status do_adjoint(tffr_plan* P, const void* cot, const void* smp, const voi
   return hip_status(e);
 }
 
+// The entropy step's range adjoint on the fields in the workspace (see tffr_debug.h).
+template <typename R>
+hipError_t launch_ent_adj_rows(tffr_plan* P, const void* smp, const void* ph, const void* da, const R* w,
+                               double* loss, void* gs, void* gph, void* gda, void* work, hipStream_t st) {
+  char* wb = (char*)work;
+  const int nparts = (P->prm.mx + P->cb - 1) / P->cb;
+  tffr::EntComb<R> ec{};
+  ec.h2 = (const cplx<R>*)(wb + P->off_h2);
+  ec.cblk = (const R*)(wb + P->off_cblk);
+  ec.cb = P->cb;
+  if (nparts <= kFuseStatsMax) {
+    ec.partials = (const double*)(wb + P->off_part);
+    ec.nparts = nparts;
+    ec.loss = loss;
+  } else {
+    ec.stats = (const double*)(wb + P->off_stats);
+  }
+  return tffr::launch_adj_rows<R>(P->geo, tables<R>(P), sample_type(P), (const cplx<R>*)(wb + P->off_hx), smp,
+                                  (const R*)ph, (const R*)da, w, (cplx<R>*)gs, (R*)gph, (R*)gda, ec, st);
+}
+
 template <typename R>
 tffr_status do_entropy_step(tffr_plan* P, const void* smp, const void* ph, const void* da, const void* uw, void* img,
                             double* loss, void* gs, void* gph, void* gda, void* work, hipStream_t st) {
@@ -356,20 +377,7 @@ tffr_status do_entropy_step(tffr_plan* P, const void* smp, const void* ph, const
   }
   if (e == hipSuccess) e = tffr::launch_ent_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, part, cblk, hx, h2, st);
   if (e == hipSuccess && !fuse) e = tffr::launch_entropy_stats(part, nparts, stats, loss, st);
-  tffr::EntComb<R> ec{};
-  ec.h2 = h2;
-  ec.cblk = cblk;
-  ec.cb = P->cb;
-  if (fuse) {
-    ec.partials = part;
-    ec.nparts = nparts;
-    ec.loss = loss;
-  } else {
-    ec.stats = stats;
-  }
-  if (e == hipSuccess)
-    e = tffr::launch_adj_rows<R>(P->geo, t, sample_type(P), hx, smp, (const R*)ph, (const R*)da, w, (cplx<R>*)gs,
-                                 (R*)gph, (R*)gda, ec, st);
+  if (e == hipSuccess) e = launch_ent_adj_rows<R>(P, smp, ph, da, w, loss, gs, gph, gda, work, st);
   return hip_status(e);
 }
 
@@ -921,6 +929,25 @@ tffr_status tffr_debug_cols(tffr_plan* P, const void* hx, void* img, tffr_stream
                                                           (cplx<double>*)img, nullptr, st)
                           : tffr::launch_fwd_cols<float>(P->geo, tables<float>(P), P->cb, (const cplx<float>*)hx,
                                                          (cplx<float>*)img, nullptr, st);
+  return hip_status(e);
+}
+
+tffr_status tffr_debug_ent_adj_rows(tffr_plan* P, const void* smp, const void* ph, const void* da, const void* uw,
+                                    double* loss, void* gs, void* gph, void* gda, void* work, tffr_stream stream) {
+  if (!P || !smp || !loss || !gs || !work) return TFFR_ERR_ARG;
+  if (P->prm.weighting == TFFR_W_USER && !uw) return TFFR_ERR_ARG;
+  if (!P->ent_fused) return TFFR_ERR_UNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if (P->dbl()) {
+    const double* w = (const double*)uw;
+    if (!w && P->prm.weighting == TFFR_W_FFR) w = (const double*)P->ffr_d.p;
+    e = launch_ent_adj_rows<double>(P, smp, ph, da, w, loss, gs, gph, gda, work, st);
+  } else {
+    const float* w = (const float*)uw;
+    if (!w && P->prm.weighting == TFFR_W_FFR) w = (const float*)P->ffr_d.p;
+    e = launch_ent_adj_rows<float>(P, smp, ph, da, w, loss, gs, gph, gda, work, st);
+  }
   return hip_status(e);
 }
 

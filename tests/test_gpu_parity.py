@@ -549,3 +549,22 @@ def test_operator_classes_match_functions():
     assert torch.equal(g, T.tffr_adjoint_op(case.plan, y))
     # d/dphi of sum |I|^2 is zero only for a single pulse; here it is a real, finite gradient
     assert torch.isfinite(ph.grad).all() and float(ph.grad.abs().sum()) > 0
+
+
+def test_entropy_step_range_adjoint_alone_repeats_the_step():
+    """tffr_debug_ent_adj_rows on the workspace an entropy step left behind reproduces that
+    step's loss and gradients bit for bit (it only reads the workspace)."""
+    case = Case(20, 90, 64, seed=81)
+    s, st = case.samples()
+    ph = case.real(case.rng.normal(0, 0.5, 20))
+    da = case.real(case.rng.normal(0, 0.004, 20))
+    img, loss, gs, gph, gda = case.plan.tffr_entropy_step(st, ph, da)
+    loss2 = torch.empty_like(loss)
+    gs2, gph2, gda2 = torch.empty_like(gs), torch.empty_like(gph), torch.empty_like(gda)
+    p = case.plan
+    for _ in range(2):
+        T._lib.check(p.lib.tffr_debug_ent_adj_rows(p.handle, T._ptr(st), T._ptr(ph), T._ptr(da), None, T._ptr(loss2),
+                                                   T._ptr(gs2), T._ptr(gph2), T._ptr(gda2), T._ptr(p.work),
+                                                   T._stream()))
+        torch.cuda.synchronize()
+        assert torch.equal(loss2, loss) and torch.equal(gs2, gs) and torch.equal(gph2, gph) and torch.equal(gda2, gda)
