@@ -799,22 +799,50 @@ __device__ __forceinline__ void cols_gather(const Geo& g, const Tab<R>& t, CellE
 // of slice n are loaded once and applied to all NC columns; column c goes to output
 // array c / CS at image column c0 + c % CS (each array's CS columns as one wide store
 // when the block is full and rows keep CS-alignment).
+// A thread's first slice (n = threadIdx.x): its start cell and up to kRunWindow taps,
+// loaded ahead (before the FFT that precedes the interpolation).
+template <typename R>
+struct SliceTaps {
+  int ys;
+  R tap[kRunWindow];
+};
+template <typename R>
+__device__ __forceinline__ SliceTaps<R> load_first_slice(const Geo& g, const Tab<R>& t) {
+  SliceTaps<R> f;
+  const int nn = min((int)threadIdx.x, g.n_pulses - 1);
+  f.ys = t.ystart[nn];
+#pragma unroll
+  for (int i = 0; i < kRunWindow; ++i) f.tap[i] = i < g.W ? t.ytap[(size_t)nn * g.W + i] : (R)0;
+  return f;
+}
+
 template <typename R, int N, int NT, int NC, int CS>
 __device__ __forceinline__ void cols_interp(const Geo& g, const Tab<R>& t, const cplx<R>* buf, int nc_valid,
-                                            cplx<R>* const* out, int c0) {
+                                            cplx<R>* const* out, int c0, const SliceTaps<R>& first) {
   const int W = g.W;
   const bool wide = CS > 1 && nc_valid == CS && g.mx % CS == 0;
   for (int nn = threadIdx.x; nn < g.n_pulses; nn += NT) {
-    const int ys = t.ystart[nn];
-    const R* tap = t.ytap + (size_t)nn * W;
     cplx<R> acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = {0, 0};
-    for (int i = 0; i < W; ++i) {
-      const R tp = tap[i];
-      const int cell = (ys + i) & (N - 1);
+    if (nn == (int)threadIdx.x && W <= kRunWindow) {  // the prefetched first slice
 #pragma unroll
-      for (int c = 0; c < NC; ++c) acc[c] = acc[c] + tp * buf[c * N + cell];
+      for (int i = 0; i < kRunWindow; ++i) {
+        if (i < W) {
+          const int cell = (first.ys + i) & (N - 1);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc[c] = acc[c] + first.tap[i] * buf[c * N + cell];
+        }
+      }
+    } else {
+      const int ys = t.ystart[nn];
+      const R* tap = t.ytap + (size_t)nn * W;
+      for (int i = 0; i < W; ++i) {
+        const R tp = tap[i];
+        const int cell = (ys + i) & (N - 1);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = acc[c] + tp * buf[c * N + cell];
+      }
     }
     if (wide) {
 #pragma unroll
@@ -921,8 +949,18 @@ __global__ __launch_bounds__(NT) void k_ent_cols(Geo g, Tab<R> t, const cplx<R>*
   const int c0 = lb * CB;
   const int ncol = min(CB, g.mx - c0);
   const int my = g.my;
+  // everything this block loads from tables is requested up front: cell entries,
+  // deapodisation factors of its pixels, the first slice's interpolation taps
   CellEntries<R, N, NT> ce;
   load_entries(t, 0, ce);
+  R dyv[DPT];
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) {
+    const int i = threadIdx.x + j * NT;
+    const int jy = (i < N / 2 ? i : i - N) + my / 2;
+    dyv[j] = (jy >= 0 && jy < my) ? t.deapy[jy] : (R)0;
+  }
+  const SliceTaps<R> first = load_first_slice(g, t);
   load_twiddles<N, NT>(tw, t.twy);
   stage_spectra<R, NT, CB>(g, hx, hs, c0, ncol);
   __syncthreads();
@@ -932,13 +970,7 @@ __global__ __launch_bounds__(NT) void k_ent_cols(Geo g, Tab<R> t, const cplx<R>*
   // image pixels: thread owns fine bins i = threadIdx.x + j NT (pixel jy = signed(i) + my/2)
   double es = 0.0, et = 0.0;
   cplx<R> v[CB][DPT];
-  R lg[CB][DPT], dyv[DPT];
-#pragma unroll
-  for (int j = 0; j < DPT; ++j) {
-    const int i = threadIdx.x + j * NT;
-    const int jy = (i < N / 2 ? i : i - N) + my / 2;
-    dyv[j] = (jy >= 0 && jy < my) ? t.deapy[jy] : (R)0;
-  }
+  R lg[CB][DPT];
 #pragma unroll
   for (int c = 0; c < CB; ++c) {
 #pragma unroll
@@ -983,7 +1015,7 @@ __global__ __launch_bounds__(NT) void k_ent_cols(Geo g, Tab<R> t, const cplx<R>*
   __syncthreads();
   lds_fft<-1, N, NT, 2 * CB>(buf, tw);  // buf and hs are contiguous: 2 CB columns
   cplx<R>* outs[2] = {h2, h1};
-  cols_interp<R, N, NT, 2 * CB, CB>(g, t, buf, ncol, outs, c0);
+  cols_interp<R, N, NT, 2 * CB, CB>(g, t, buf, ncol, outs, c0, first);
 }
 
 // Image entropy from the per-block sums: E = ln S - (1/S) sum a ln a.  One block.
@@ -1060,9 +1092,10 @@ __global__ __launch_bounds__(NT) void k_adj_cols(Geo g, Tab<R> t, const cplx<R>*
     buf[idx] = v;
   }
   __syncthreads();
+  const SliceTaps<R> first = load_first_slice(g, t);
   lds_fft<-1, N, NT, CB>(buf, tw);
   cplx<R>* outs[1] = {hx};
-  cols_interp<R, N, NT, CB, CB>(g, t, buf, ncol, outs, c0);
+  cols_interp<R, N, NT, CB, CB>(g, t, buf, ncol, outs, c0, first);
 }
 
 // Range stage, type 2: per slice, divide by the kernel transform, zero-pad, forward FFT
@@ -1249,9 +1282,10 @@ __global__ __launch_bounds__(NT) void k_coord_cols(Geo g, Tab<R> t, const cplx<R
     buf[CB * N + idx] = ((R)jp * ypix) * v;
   }
   __syncthreads();
+  const SliceTaps<R> first = load_first_slice(g, t);
   lds_fft<-1, N, NT, 2 * CB>(buf, tw);
   cplx<R>* outs[2] = {h0, h1};
-  cols_interp<R, N, NT, 2 * CB, CB>(g, t, buf, ncol, outs, c0);
+  cols_interp<R, N, NT, 2 * CB, CB>(g, t, buf, ncol, outs, c0, first);
 }
 
 // Range stage: per slice, rows X h0 and h1 (deapodised, zero-padded), batched forward
