@@ -131,6 +131,16 @@ def cpu_baseline(wl, k, ku, s, phase, dalong, cols):
     from oracle import pipeline as OP
 
     threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
+    cpu_model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next(line.split(":", 1)[1].strip() for line in f if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    try:
+        blas = np.show_config(mode="dicts")["Build Dependencies"]["blas"]["name"]
+    except Exception:  # noqa: BLE001 - informational only
+        blas = "unknown BLAS"
     prob = OP.Problem(k=k, ku=ku, mx=wl.m, my=wl.m, fov_x=wl.fov, fov_y=wl.fov)
     rng = np.random.default_rng(5)
     col_idx = np.sort(rng.choice(wl.m, cols, replace=False))
@@ -156,9 +166,11 @@ def cpu_baseline(wl, k, ku, s, phase, dalong, cols):
         "unit": "Msamples/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": (f"FP64 NumPy oracle: weights for all {wl.n_samples} samples ({t_w:.2f} s), forward on "
-                   f"{cols}/{wl.m} image columns ({t_f:.2f} s), entropy gradient + adjoint on {rows}/"
-                   f"{wl.n_pulses} pulses ({t_a:.2f} s); full step extrapolated linearly to {full:.1f} s"),
+        "sample": (f"FP64 NumPy oracle on {cpu_model} ({blas} with {threads} threads for the matrix products; "
+                   f"NumPy's elementwise exponentials run on one core): weights for all {wl.n_samples} samples "
+                   f"({t_w:.2f} s), forward on {cols}/{wl.m} image columns ({t_f:.2f} s), entropy gradient + "
+                   f"adjoint on {rows}/{wl.n_pulses} pulses ({t_a:.2f} s); full step extrapolated linearly to "
+                   f"{full:.1f} s"),
     }, img_cols, col_idx
 
 
