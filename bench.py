@@ -310,7 +310,7 @@ def main():
     # points with the launch configuration used inside tffr_entropy_step (the range
     # kernel the plan picked; the fused entropy azimuth kernel); the slower is reported
     hx = torch.empty((wl.n_pulses, wl.m), dtype=torch.complex64, device=dev)
-    h2 = torch.empty_like(hx)
+    h12 = torch.empty((wl.n_pulses, wl.m, 2), dtype=torch.complex64, device=dev)
     img_k = torch.empty((wl.m, wl.m), dtype=torch.complex64, device=dev)
     rows_name = "k_fwd_rows_run" if plan.range_mode == 1 else "k_fwd_rows"
 
@@ -319,7 +319,7 @@ def main():
                                               T._ptr(hx), T._stream()))
 
     def azimuth_stage():
-        T._lib.check(plan.lib.tffr_debug_ent_cols(plan.handle, T._ptr(hx), T._ptr(img_k), T._ptr(h2),
+        T._lib.check(plan.lib.tffr_debug_ent_cols(plan.handle, T._ptr(hx), T._ptr(img_k), T._ptr(h12),
                                                   T._ptr(plan.work), T._stream()))
 
     def range_adjoint():

@@ -133,7 +133,7 @@ tffr_status tffr_plan_create_xy(const tffr_params *p, const double *kx, const do
 void tffr_plan_destroy(tffr_plan *plan);
 
 /* Bytes of caller-owned device workspace every forward / adjoint / entropy / weights
- * call needs (two [n_pulses][mx] complex arrays of per-slice range spectra plus
+ * call needs (three [n_pulses][mx] complex arrays of per-slice range spectra plus
  * reduction scratch).  0 for NULL. */
 size_t tffr_workspace_bytes(const tffr_plan *plan);
 

@@ -42,13 +42,14 @@ tffr_status tffr_debug_plan_config(const tffr_plan *plan, int32_t *range_mode, i
                                    int32_t *ent_fused);
 
 /* Azimuth stage of the fused entropy step alone (the launch inside tffr_entropy_step):
- *   d_hx     [n_pulses][mx] range spectra in; overwritten with the adjoint azimuth
- *            transform of I (ln|I|^2 - c_b), c_b = ln of column block b's mean |I|^2
+ *   d_hx     [n_pulses][mx] range spectra, read only
  *   d_image  [mx][my] written (as tffr_debug_cols)
- *   d_h2     [n_pulses][mx] written: adjoint azimuth transform of I
+ *   d_h12    [n_pulses][mx][2] complex written: (h1, h2) interleaved, h1 the adjoint
+ *            azimuth transform of I (ln|I|^2 - c_b) with c_b = ln of column block b's mean
+ *            |I|^2, h2 that of I
  *   d_work   workspace of the plan (receives the entropy partial sums and the c_b)
  * TFFR_ERR_UNSUPPORTED when the plan's entropy step does not use the fused kernel. */
-tffr_status tffr_debug_ent_cols(tffr_plan *plan, void *d_hx, void *d_image, void *d_h2,
+tffr_status tffr_debug_ent_cols(tffr_plan *plan, const void *d_hx, void *d_image, void *d_h12,
                                 void *d_work, tffr_stream stream);
 
 /* Range adjoint of the fused entropy step alone (the last launch inside

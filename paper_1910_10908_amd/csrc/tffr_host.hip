@@ -142,7 +142,7 @@ struct tffr_plan {
   // workspace layout
   bool ent_fused = false;  // entropy step uses the fused azimuth kernel
   int coord_cb = 0;        // azimuth block width of the coordinate-gradient kernels (0: unsupported)
-  size_t off_hx = 0, off_h2 = 0, off_cblk = 0, off_part = 0, off_stats = 0, off_kept = 0, off_count = 0, off_status = 0, off_gband = 0, off_zband = 0,
+  size_t off_hx = 0, off_h12 = 0, off_cblk = 0, off_part = 0, off_stats = 0, off_kept = 0, off_count = 0, off_status = 0, off_gband = 0, off_zband = 0,
          off_dband = 0, work_bytes = 0;
   bool dbl() const { return prm.dtype == TFFR_C128; }
   size_t csize() const { return dbl() ? 16 : 8; }
@@ -331,7 +331,7 @@ hipError_t launch_ent_adj_rows(tffr_plan* P, const void* smp, const void* ph, co
   char* wb = (char*)work;
   const int nparts = (P->prm.mx + P->cb - 1) / P->cb;
   tffr::EntComb<R> ec{};
-  ec.h2 = (const cplx<R>*)(wb + P->off_h2);
+  ec.h12 = (const cplx<R>*)(wb + P->off_h12);
   ec.cblk = (const R*)(wb + P->off_cblk);
   ec.cb = P->cb;
   if (nparts <= kFuseStatsMax) {
@@ -356,10 +356,10 @@ tffr_status do_entropy_step(tffr_plan* P, const void* smp, const void* ph, const
   double* part = (double*)(wb + P->off_part);
   double* stats = (double*)(wb + P->off_stats);
   const int nparts = (P->prm.mx + P->cb - 1) / P->cb;
-  cplx<R>* h2 = (cplx<R>*)(wb + P->off_h2);
+  cplx<R>* h12 = (cplx<R>*)(wb + P->off_h12);
   R* cblk = (R*)(wb + P->off_cblk);
   // range stage; azimuth forward + entropy sums + adjoint azimuth transforms of the two
-  // gradient fields in one kernel (h1 overwrites the range spectra in place); range
+  // gradient fields in one kernel (written interleaved); range
   // adjoint combining the fields with the global entropy sums
   hipError_t e = tffr::launch_fwd_rows<R>(P->geo, t, sample_type(P), smp, (const R*)ph, (const R*)da, w, hx, 1, st);
   // few partial sums: every adjoint block reduces them itself (no separate launch)
@@ -375,7 +375,7 @@ tffr_status do_entropy_step(tffr_plan* P, const void* smp, const void* ph, const
                                    (R*)gph, (R*)gda, tffr::EntComb<R>{}, st);
     return hip_status(e);
   }
-  if (e == hipSuccess) e = tffr::launch_ent_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, part, cblk, hx, h2, st);
+  if (e == hipSuccess) e = tffr::launch_ent_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, part, cblk, h12, st);
   if (e == hipSuccess && !fuse) e = tffr::launch_entropy_stats(part, nparts, stats, loss, st);
   if (e == hipSuccess) e = launch_ent_adj_rows<R>(P, smp, ph, da, w, loss, gs, gph, gda, work, st);
   return hip_status(e);
@@ -677,8 +677,8 @@ tffr_status plan_create(const tffr_params* p, const double* k, const double* ku,
   size_t off = 0;
   P->off_hx = off;
   off = align_up(off + (size_t)p->n_pulses * p->mx * csz);
-  P->off_h2 = off;  // entropy step: second gradient field of the range spectra
-  off = align_up(off + (size_t)p->n_pulses * p->mx * csz);
+  P->off_h12 = off;  // entropy step: the two gradient fields, interleaved [n_pulses][mx][2]
+  off = align_up(off + 2 * (size_t)p->n_pulses * p->mx * csz);
   P->off_cblk = off;  // entropy step: centring constant per column block
   off = align_up(off + (P->dbl() ? sizeof(double) : sizeof(float)) * (size_t)((p->mx + P->cb - 1) / P->cb));
   P->off_part = off;
@@ -825,14 +825,14 @@ tffr_status tffr_coord_grad(tffr_plan* P, const void* cot, const void* smp, cons
     if (!w && P->prm.weighting == TFFR_W_FFR) w = (const double*)P->ffr_d.p;
     e = tffr::launch_coord_grad<double>(P->geo, tables<double>(P), P->coord_cb, sample_type(P),
                                         (const cplx<double>*)cot, smp, (const double*)ph, (const double*)da, w,
-                                        (cplx<double>*)(wb + P->off_hx), (cplx<double>*)(wb + P->off_h2),
+                                        (cplx<double>*)(wb + P->off_hx), (cplx<double>*)(wb + P->off_h12),
                                         (double*)gkx, (double*)gky, st);
   } else {
     const float* w = (const float*)uw;
     if (!w && P->prm.weighting == TFFR_W_FFR) w = (const float*)P->ffr_d.p;
     e = tffr::launch_coord_grad<float>(P->geo, tables<float>(P), P->coord_cb, sample_type(P),
                                        (const cplx<float>*)cot, smp, (const float*)ph, (const float*)da, w,
-                                       (cplx<float>*)(wb + P->off_hx), (cplx<float>*)(wb + P->off_h2),
+                                       (cplx<float>*)(wb + P->off_hx), (cplx<float>*)(wb + P->off_h12),
                                        (float*)gkx, (float*)gky, st);
   }
   return hip_status(e);
@@ -959,8 +959,8 @@ tffr_status tffr_debug_plan_config(const tffr_plan* P, int32_t* range_mode, int3
   return TFFR_OK;
 }
 
-tffr_status tffr_debug_ent_cols(tffr_plan* P, void* hx, void* img, void* h2, void* work, tffr_stream stream) {
-  if (!P || !hx || !img || !h2 || !work) return TFFR_ERR_ARG;
+tffr_status tffr_debug_ent_cols(tffr_plan* P, const void* hx, void* img, void* h12, void* work, tffr_stream stream) {
+  if (!P || !hx || !img || !h12 || !work) return TFFR_ERR_ARG;
   if (!P->ent_fused) return TFFR_ERR_UNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   char* wb = (char*)work;
@@ -968,10 +968,10 @@ tffr_status tffr_debug_ent_cols(tffr_plan* P, void* hx, void* img, void* h2, voi
   hipError_t e =
       P->dbl() ? tffr::launch_ent_cols<double>(P->geo, tables<double>(P), P->cb, (const cplx<double>*)hx,
                                                (cplx<double>*)img, part, (double*)(wb + P->off_cblk),
-                                               (cplx<double>*)hx, (cplx<double>*)h2, st)
+                                               (cplx<double>*)h12, st)
                : tffr::launch_ent_cols<float>(P->geo, tables<float>(P), P->cb, (const cplx<float>*)hx,
                                               (cplx<float>*)img, part, (float*)(wb + P->off_cblk),
-                                              (cplx<float>*)hx, (cplx<float>*)h2, st);
+                                              (cplx<float>*)h12, st);
   return hip_status(e);
 }
 

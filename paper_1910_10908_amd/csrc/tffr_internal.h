@@ -63,13 +63,14 @@ struct Tab {
 
 enum SampleType { ST_C64 = 0, ST_C128 = 1, ST_H2 = 2 };
 
-// Entropy-step input of the range adjoint: with h2 non-null its range-spectra cotangent
-// is alpha h1 + (beta + alpha cblk[column / cb]) h2 (h1 is the usual hx argument), where
-// alpha, beta come from the global entropy sums: reduced by every block from nparts
-// partial pairs (then block 0 writes *loss), or read from stats = {S, E}.
+// Entropy-step input of the range adjoint: with h12 non-null (the two gradient fields
+// interleaved, [n_pulses][mx][2] = (h1, h2)) its range-spectra cotangent is
+// alpha h1 + (beta + alpha cblk[column / cb]) h2, where alpha, beta come from the global
+// entropy sums: reduced by every block from nparts partial pairs (then block 0 writes
+// *loss), or read from stats = {S, E}.
 template <typename R>
 struct EntComb {
-  const cplx<R>* h2;
+  const cplx<R>* h12;
   const R* cblk;
   int cb;
   const double* partials;
@@ -93,7 +94,7 @@ hipError_t launch_adj_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>*
 hipError_t launch_entropy_stats(const double* partials, int nparts, double* stats, double* loss, hipStream_t st);
 template <typename R>
 hipError_t launch_ent_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>* hx, cplx<R>* img,
-                           double* partials, R* cblk, cplx<R>* h1, cplx<R>* h2, hipStream_t st);
+                           double* partials, R* cblk, cplx<R>* h12, hipStream_t st);
 template <typename R>
 hipError_t launch_adj_rows(const Geo& g, const Tab<R>& t, int stype, const cplx<R>* hx,
                            const void* samples, const R* phase, const R* dalong, const R* w,

@@ -816,7 +816,10 @@ __device__ __forceinline__ SliceTaps<R> load_first_slice(const Geo& g, const Tab
   return f;
 }
 
-template <typename R, int N, int NT, int NC, int CS>
+// IL (interleaved, NC = 2 CS): a single output array [n_pulses][mx][2] takes column
+// CS + c (first value) and column c (second value) of image column c0 + c, so each slice's
+// block is one contiguous store of 2 CS values.
+template <typename R, int N, int NT, int NC, int CS, bool IL = false>
 __device__ __forceinline__ void cols_interp(const Geo& g, const Tab<R>& t, const cplx<R>* buf, int nc_valid,
                                             cplx<R>* const* out, int c0, const SliceTaps<R>& first) {
   const int W = g.W;
@@ -844,7 +847,25 @@ __device__ __forceinline__ void cols_interp(const Geo& g, const Tab<R>& t, const
         for (int c = 0; c < NC; ++c) acc[c] = acc[c] + tp * buf[c * N + cell];
       }
     }
-    if (wide) {
+    if constexpr (IL) {
+      cplx<R>* o = out[0] + ((size_t)nn * g.mx + c0) * 2;
+      if (nc_valid == CS) {
+        CVec<R, 2 * CS> v;
+#pragma unroll
+        for (int c = 0; c < CS; ++c) {
+          v.v[2 * c] = acc[CS + c];
+          v.v[2 * c + 1] = acc[c];
+        }
+        *reinterpret_cast<CVec<R, 2 * CS>*>(o) = v;
+      } else {
+#pragma unroll
+        for (int c = 0; c < CS; ++c)
+          if (c < nc_valid) {
+            o[2 * c] = acc[CS + c];
+            o[2 * c + 1] = acc[c];
+          }
+      }
+    } else if (wide) {
 #pragma unroll
       for (int o = 0; o < NC / CS; ++o) {
         CVec<R, CS> v;
@@ -936,9 +957,9 @@ __global__ __launch_bounds__(NT) void k_fwd_cols(Geo g, Tab<R> t, const cplx<R>*
 // LDS: the two fields' fine columns [2][CB][N] reuse the staged-spectra space.  h1 may
 // be hx itself: a block reads only its own columns of hx, all before its first write.
 template <typename R, int LOGN, int NT, int CB>
-__global__ __launch_bounds__(NT) void k_ent_cols(Geo g, Tab<R> t, const cplx<R>* hx, cplx<R>* __restrict__ img,
-                                                 double* __restrict__ partials, R* __restrict__ cblk, cplx<R>* h1,
-                                                 cplx<R>* __restrict__ h2) {
+__global__ __launch_bounds__(NT) void k_ent_cols(Geo g, Tab<R> t, const cplx<R>* __restrict__ hx,
+                                                 cplx<R>* __restrict__ img, double* __restrict__ partials,
+                                                 R* __restrict__ cblk, cplx<R>* __restrict__ h12) {
   constexpr int N = 1 << LOGN;
   constexpr int DPT = N / NT;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1014,8 +1035,8 @@ __global__ __launch_bounds__(NT) void k_ent_cols(Geo g, Tab<R> t, const cplx<R>*
   }
   __syncthreads();
   lds_fft<-1, N, NT, 2 * CB>(buf, tw);  // buf and hs are contiguous: 2 CB columns
-  cplx<R>* outs[2] = {h2, h1};
-  cols_interp<R, N, NT, 2 * CB, CB>(g, t, buf, ncol, outs, c0, first);
+  cplx<R>* outs[1] = {h12};
+  cols_interp<R, N, NT, 2 * CB, CB, true>(g, t, buf, ncol, outs, c0, first);
 }
 
 // Image entropy from the per-block sums: E = ln S - (1/S) sum a ln a.  One block.
@@ -1128,7 +1149,7 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
   load_twiddles<N, NT>(tw, t.twx);
   const float* poly = load_poly<NT>(g, t.poly, lpoly);
   const cplx<R>* in = hx + (size_t)n * mx;
-  if (ec.h2) {
+  if (ec.h12) {
     // entropy step: the range-spectra cotangent is alpha h1 + (beta + alpha cc[col block]) h2
     double S, T;
     if (ec.partials) {
@@ -1145,14 +1166,15 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
       T = S > 0.0 ? S * (log(S) - ec.stats[1]) : 0.0;
     }
     const double al = S > 0.0 ? -2.0 / S : 0.0, be = S > 0.0 ? 2.0 * T / (S * S) : 0.0;
-    const cplx<R>* in2 = ec.h2 + (size_t)n * mx;
+    const CVec<R, 2>* in12 = reinterpret_cast<const CVec<R, 2>*>(ec.h12) + (size_t)n * mx;
     for (int i = threadIdx.x; i < N; i += NT) {
       const int jp = i < N / 2 ? i : i - N;
       const int jx = jp + mx / 2;
       cplx<R> v = {0, 0};
       if (jx >= 0 && jx < mx) {
         const R c2 = (R)(be + al * (double)ec.cblk[jx / ec.cb]);
-        v = t.deapx[jx] * ((R)al * in[jx] + c2 * in2[jx]);
+        const CVec<R, 2> f = in12[jx];
+        v = t.deapx[jx] * ((R)al * f.v[0] + c2 * f.v[1]);
       }
       buf[i] = v;
     }
@@ -1756,7 +1778,7 @@ hipError_t launch_adj_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>*
 
 template <typename R>
 hipError_t launch_ent_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>* hx, cplx<R>* img, double* partials,
-                           R* cblk, cplx<R>* h1, cplx<R>* h2, hipStream_t st) {
+                           R* cblk, cplx<R>* h12, hipStream_t st) {
   const size_t nfy = (size_t)1 << g.lognfy;
   const size_t lds = sizeof(cplx<R>) * (nfy * cb + std::max<size_t>((size_t)g.n_pulses * cb, nfy * cb) + nfy / 64 + 64);
   const int grid = (g.mx + cb - 1) / cb;
@@ -1766,7 +1788,7 @@ hipError_t launch_ent_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>*
       auto fn = k_ent_cols<R, L, NT, CB>;
       hipError_t e = allow_lds((const void*)fn, lds);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), lds, st, g, t, hx, img, partials, cblk, h1, h2);
+      hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), lds, st, g, t, hx, img, partials, cblk, h12);
       return hipGetLastError();
     })
   })
@@ -1932,7 +1954,7 @@ hipError_t launch_fft(int log2n, int batch, int sign, int max_radix, const cplx<
   template hipError_t launch_adj_cols<R>(const Geo&, const Tab<R>&, int, const cplx<R>*, cplx<R>*, const double*, \
                                          const double*, int, double*, hipStream_t);                             \
   template hipError_t launch_ent_cols<R>(const Geo&, const Tab<R>&, int, const cplx<R>*, cplx<R>*, double*, R*,   \
-                                         cplx<R>*, cplx<R>*, hipStream_t);                                     \
+                                         cplx<R>*, hipStream_t);                                               \
   template hipError_t launch_adj_rows<R>(const Geo&, const Tab<R>&, int, const cplx<R>*, const void*, const R*, \
                                          const R*, const R*, cplx<R>*, R*, R*, const EntComb<R>&, hipStream_t); \
   template hipError_t launch_coord_grad<R>(const Geo&, const Tab<R>&, int, int, const cplx<R>*, const void*,       \

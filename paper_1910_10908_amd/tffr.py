@@ -253,15 +253,13 @@ def tffr_debug_cols(plan, hx, out=None):
 
 def tffr_debug_ent_cols(plan, hx):
     """Fused entropy-step azimuth stage alone: range spectra -> (image, h1, h2), where h1
-    and h2 are the adjoint azimuth transforms of I (ln|I|^2 - c_b) and of I; hx is left
-    unchanged (the kernel works on a copy)."""
+    and h2 are the adjoint azimuth transforms of I (ln|I|^2 - c_b) and of I."""
     plan._chk(hx, (plan.params.n_pulses, plan.params.mx), plan.ctype, "hx")
-    h1 = hx.clone()
     img = torch.empty(plan.shape_image, dtype=plan.ctype, device=plan.device)
-    h2 = torch.empty_like(hx)
-    _lib.check(plan.lib.tffr_debug_ent_cols(plan.handle, _ptr(h1), _ptr(img), _ptr(h2), _ptr(plan.work),
+    h12 = torch.empty((plan.params.n_pulses, plan.params.mx, 2), dtype=plan.ctype, device=plan.device)
+    _lib.check(plan.lib.tffr_debug_ent_cols(plan.handle, _ptr(hx), _ptr(img), _ptr(h12), _ptr(plan.work),
                                             _stream()), "tffr_debug_ent_cols")
-    return img, h1, h2
+    return img, h12[..., 0], h12[..., 1]
 
 
 def tffr_debug_fft(x, sign, max_radix=8):
