@@ -123,14 +123,33 @@ def kernel_time(torch, fn, reps=200):
     return e0.elapsed_time(e1) / reps * 1e-3  # seconds
 
 
-def cpu_baseline(wl, k, ku, s, phase, dalong, cols):
-    """The FP64 oracle timed on a bounded sample of the same step, scaled to Msamples/s."""
-    import oracle
+def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
+    """GB/s of a plain device-to-device copy (read + write bytes over its duration): the
+    bandwidth a streaming kernel reaches on this GPU, a second denominator beside the
+    published HBM peak."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    t = kernel_time(torch, lambda: dst.copy_(src), reps)
+    del src, dst
+    return 2 * nbytes / t / 1e9
+
+
+def cpu_baseline(wl, k, ku, s, phase, dalong, cols, threads=None):
+    """The FP64 oracle timed on a bounded sample of the same step, scaled to Msamples/s.
+    With `threads` the BLAS pool is limited to that many threads for the timed work."""
+    if threads is not None:
+        from threadpoolctl import threadpool_limits
+
+        with threadpool_limits(limits=threads):
+            return _cpu_baseline(wl, k, ku, s, phase, dalong, cols, str(threads))
+    return _cpu_baseline(wl, k, ku, s, phase, dalong, cols,
+                         os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count()))
+
+
+def _cpu_baseline(wl, k, ku, s, phase, dalong, cols, threads):
     from oracle import entropy as OE
-    from oracle import nudft as ON
     from oracle import pipeline as OP
 
-    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
     cpu_model = "unknown CPU"
     try:
         with open("/proc/cpuinfo") as f:
@@ -174,6 +193,12 @@ def cpu_baseline(wl, k, ku, s, phase, dalong, cols):
     }, img_cols, col_idx
 
 
+def accuracy(got, ref):
+    """rel-L2 and peak error (dB of the largest error over the largest reference value)."""
+    return {"rel_l2_vs_fp64": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            "peak_db": float(20 * np.log10(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))}
+
+
 def sweep(args):
     """Every workload at its own size and precision: the tFFR entropy step, the plain-NUFFT
     (quadrature) step and the plain-FFR step (weights solved inside the step), each timed
@@ -182,6 +207,7 @@ def sweep(args):
     own time for the step on the host (bounded sample, extrapolated)."""
     import torch
 
+    from oracle import pipeline as OP
     from paper_1910_10908_amd import scenes
     from paper_1910_10908_amd import tffr as T
 
@@ -222,13 +248,40 @@ def sweep(args):
                 rec[label]["peak_device_MiB"] = torch.cuda.max_memory_allocated() / 2 ** 20
                 img = st.img.cpu().numpy().astype(np.complex128)
             del plan, st
+        img16 = None
+        if dtype == T.C64 and wl.name == "precision_2k":
+            # the same step on samples stored as two IEEE halves (FP32 arithmetic)
+            h = torch.view_as_real(s).to(torch.float16).contiguous()
+            prm = T.default_params(n_pulses=wl.n_pulses, n_freq=wl.n_freq, mx=wl.m, my=wl.m, fov_x=wl.fov,
+                                   fov_y=wl.fov, weighting=T.W_TFFR, kernel_width=wl.kernel_width,
+                                   dtype=T.C64_FP16IN)
+            plan = T.Plan(prm, k, ku, dev)
+            st = Step(T, plan, h, ph, da)
+            ms_e, _ = time_step(torch, st, steps, 5, graph=False)
+            ms_g, _ = time_step(torch, st, steps, 5, graph=True)
+            ms = min(ms_e, ms_g)
+            rec["tffr_fp16_samples"] = {"ms_per_step": ms, "Msamples_per_s": wl.n_samples / (ms * 1e-3) / 1e6,
+                                        "timing": "hip_graph" if ms_g < ms_e else "eager"}
+            st()
+            torch.cuda.synchronize()
+            img16 = st.img.cpu().numpy().astype(np.complex128)
+            hr = h.cpu().numpy().astype(np.float64)
+            s16 = hr[..., 0] + 1j * hr[..., 1]
+            del plan, st, h
         cols = max(2, min(48, int(48 * 524288 / wl.n_samples)))
-        base, ref_cols, col_idx = cpu_baseline(wl, k, ku, s.cpu().numpy().astype(np.complex128),
-                                               np.zeros(wl.n_pulses), np.zeros(wl.n_pulses), cols)
-        rec["accuracy"] = {"rel_l2_vs_fp64": float(np.linalg.norm(img[col_idx] - ref_cols) /
-                                                   np.linalg.norm(ref_cols)),
-                           "sample": f"{len(col_idx)} of {wl.m} image columns"}
+        s_np = s.cpu().numpy().astype(np.complex128)
+        zeros = np.zeros(wl.n_pulses)
+        base, ref_cols, col_idx = cpu_baseline(wl, k, ku, s_np, zeros, zeros, cols)
+        rec["accuracy"] = dict(accuracy(img[col_idx], ref_cols), sample=f"{len(col_idx)} of {wl.m} image columns")
         rec["cpu_oracle"] = base
+        if wl.n_samples <= 524288:
+            # the oracle on one core too, for context against the paper's serial timings
+            rec["cpu_oracle_1core"] = cpu_baseline(wl, k, ku, s_np, zeros, zeros, cols, threads=1)[0]
+        if img16 is not None:
+            prob = OP.Problem(k=k, ku=ku, mx=wl.m, my=wl.m, fov_x=wl.fov, fov_y=wl.fov)
+            ref16 = OP.image_columns(prob, s16, col_idx, zeros, zeros)
+            rec["tffr_fp16_samples"]["accuracy_vs_rounded_inputs"] = accuracy(img16[col_idx], ref16)
+            rec["tffr_fp16_samples"]["accuracy_vs_fp64_inputs"] = accuracy(img16[col_idx], ref_cols)
         print(json.dumps(rec), flush=True)
         del inp, s, img
 
@@ -353,6 +406,7 @@ def main():
     t_k, alg_bytes = kernels[kname]
     achieved = alg_bytes / t_k / 1e9
     traffic = passes[kname]["traffic"]
+    copy_gbs = copy_bandwidth(torch)
     kept = plan.tffr_kept_count()
 
     out = {
@@ -374,7 +428,7 @@ def main():
                    "parallelism": "single_gpu"},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel_us": t_k * 1e6,
-                     "alg_bytes": alg_bytes},
+                     "alg_bytes": alg_bytes, "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "passes": passes,
         "kept_count": kept,
         "graph_replay_matches_eager": replay_ok,
@@ -415,10 +469,7 @@ def main():
         step()
         torch.cuda.synchronize()
         got = step.img.cpu().numpy()[col_idx].astype(np.complex128)
-        err = np.linalg.norm(got - ref_cols) / np.linalg.norm(ref_cols)
-        pk = 20 * np.log10(np.max(np.abs(got - ref_cols)) / np.max(np.abs(ref_cols)))
-        out["accuracy"] = {"rel_l2_vs_fp64": float(err), "peak_db": float(pk),
-                           "sample": f"{len(col_idx)} of {wl.m} image columns, full height"}
+        out["accuracy"] = dict(accuracy(got, ref_cols), sample=f"{len(col_idx)} of {wl.m} image columns, full height")
         for name, prm in (("tffr_width6", params(T.W_TFFR, 6)),
                           ("tffr_literal_algorithm1", params(T.W_TFFR, width, T.GRID_LITERAL))):
             if "comparisons" in out and "error" not in out["comparisons"].get(name, {"error": 1}):

@@ -177,11 +177,24 @@ __device__ __forceinline__ void load_twiddles(cplx<R>* tw, const cplx<R>* __rest
   for (int i = threadIdx.x; i < tw_entries<N>(); i += NT) tw[i] = g[i];
 }
 
+// LDS position of element j of a transform between two FFT stages (the range kernels'
+// layout).  A stage's stores y[(i - k) RAD + k + r P] put consecutive lanes RAD apart
+// when P = 1 (and in runs of P when P is small), so a plain layout sends many lanes of a
+// store to the same bank.  The position XORs bits 0..4 of j with bits 5..8 (into bits
+// 0..3) and 6..7 (into bits 3..4): a bijection that moves nothing across a 32-element
+// block, so the loads x[i + r N/RAD] of consecutive lanes stay on distinct banks while
+// the small-P stores spread out.  Transforms are still read from and written back to
+// the natural layout; only the values between stages live in this one.  For a and b
+// with no common bits the position of a + b is swz(a) ^ swz(b) (swz is linear over
+// XOR): one swz per butterfly, then one XOR with a constant per element.
+__host__ __device__ constexpr int swz(int j) { return j ^ ((j >> 5) & 15) ^ (((j >> 6) & 3) << 3); }
+
 // One Stockham autosort stage of radix RAD after spans P, on NBAT transforms stored
 // back to back (in place: all reads, barrier, all writes, barrier).  Butterfly i of a
 // transform reads x[i + r N/RAD], applies exp(SIGN 2 pi i r k / (P RAD)) with
-// k = i mod P, and writes y[(i - k) RAD + k + r P].
-template <int SIGN, int N, int RAD, int P, int NT, int NBAT, typename R>
+// k = i mod P, and writes y[(i - k) RAD + k + r P].  SWI / SWO: input / output in the
+// inter-stage layout (swz).
+template <int SIGN, int N, int RAD, int P, int NT, int NBAT, bool SWI, bool SWO, typename R>
 __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* tw) {
   constexpr int NB = N / RAD;
   constexpr int TOT = NB * NBAT;
@@ -193,8 +206,9 @@ __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* tw) {
     if (TOT % NT == 0 || bf < TOT) {
       const int col = bf / NB, i = bf - col * NB;
       const cplx<R>* x = buf + col * N;
+      const int si = swz(i);
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) v[b][r] = x[i + r * NB];
+      for (int r = 0; r < RAD; ++r) v[b][r] = x[SWI ? (si ^ swz(r * NB)) : (i + r * NB)];
     }
   }
   __syncthreads();
@@ -231,19 +245,20 @@ __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* tw) {
       dft<SIGN, RAD>(v[b]);
       const int j = (i - k) * RAD + k;
       cplx<R>* y = buf + col * N;
+      const int sj = swz(j);
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) y[j + r * P] = v[b][r];
+      for (int r = 0; r < RAD; ++r) y[SWO ? (sj ^ swz(r * P)) : (j + r * P)] = v[b][r];
     }
   }
   __syncthreads();
 }
 
-template <int SIGN, int N, int P, int NT, int NBAT, int MAXRAD, typename R>
+template <int SIGN, int N, int P, int NT, int NBAT, int MAXRAD, bool SWZ, typename R>
 __device__ __forceinline__ void fft_from(cplx<R>* buf, const cplx<R>* tw) {
   if constexpr (P < N) {
     constexpr int RAD = (N / P) >= MAXRAD ? MAXRAD : (N / P);
-    fft_stage<SIGN, N, RAD, P, NT, NBAT>(buf, tw);
-    fft_from<SIGN, N, P * RAD, NT, NBAT, MAXRAD>(buf, tw);
+    fft_stage<SIGN, N, RAD, P, NT, NBAT, SWZ && (P > 1), SWZ && (P * RAD < N)>(buf, tw);
+    fft_from<SIGN, N, P * RAD, NT, NBAT, MAXRAD, SWZ>(buf, tw);
   }
 }
 
@@ -253,9 +268,12 @@ __device__ __forceinline__ void fft_from(cplx<R>* buf, const cplx<R>* tw) {
 // Stages of radix MAXRAD (8 or 16) and one smaller last stage.  Radix 16 takes fewer LDS
 // passes and, in the dense-slice range kernel, fewer registers (more workgroups per CU);
 // radix 8 keeps more threads busy per stage where a workgroup has few butterflies.
-template <int SIGN, int N, int NT, int NBAT = 1, int MAXRAD = 8, typename R>
+// SWZ: values between stages in the bank-spreading layout (swz).  It pays in the
+// one-transform range kernels; in the batched azimuth transforms the per-element
+// addresses cost more registers than the conflicts cost time.
+template <int SIGN, int N, int NT, int NBAT = 1, int MAXRAD = 8, bool SWZ = false, typename R>
 __device__ __forceinline__ void lds_fft(cplx<R>* buf, const cplx<R>* tw) {
-  fft_from<SIGN, N, 1, NT, NBAT, MAXRAD>(buf, tw);
+  fft_from<SIGN, N, 1, NT, NBAT, MAXRAD, SWZ>(buf, tw);
 }
 
 // ----------------------------------------------------------------------------- geometry
@@ -596,7 +614,7 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(Geo g, Tab<R> t, int stype, con
     const int jx = threadIdx.x + j * NT;
     dx[j] = jx < mx ? t.deapx[jx] : (R)0;
   }
-  lds_fft<+1, N, NT>(buf, tw);
+  lds_fft<+1, N, NT, 1, 8, true>(buf, tw);
 #pragma unroll
   for (int j = 0; j < DPT; ++j) {
     const int jx = threadIdx.x + j * NT;
@@ -715,7 +733,7 @@ __global__ __launch_bounds__(NT) void k_fwd_rows_run(Geo g, Tab<R> t, int stype,
     const int jx = threadIdx.x + j * NT;
     dx[j] = jx < mx ? t.deapx[jx] : (R)0;
   }
-  lds_fft<+1, N, NT, 1, 16>(buf, tw);
+  lds_fft<+1, N, NT, 1, 16, true>(buf, tw);
 #pragma unroll
   for (int j = 0; j < DPT; ++j) {
     const int jx = threadIdx.x + j * NT;
@@ -1189,7 +1207,7 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
   const double ku = t.ku[n];
   const R halfw = (R)(0.5 * g.W), inv_halfw = (R)(2.0 / g.W), beta = es_shape<R>(g);
   __syncthreads();
-  lds_fft<-1, N, NT>(buf, tw);
+  lds_fft<-1, N, NT, 1, 8, true>(buf, tw);
   double acc_phase = 0.0;
   for (int p = threadIdx.x; p < g.n_freq; p += NT) {
     const double kp = k_next;
@@ -1638,7 +1656,7 @@ __global__ __launch_bounds__(NT) void k_fft(const cplx<R>* __restrict__ in, cplx
   load_twiddles<N, NT>(twl, tw);
   for (int i = threadIdx.x; i < N; i += NT) buf[i] = in[off + i];
   __syncthreads();
-  lds_fft<SIGN, N, NT, 1, MAXRAD>(buf, twl);
+  lds_fft<SIGN, N, NT, 1, MAXRAD, true>(buf, twl);
   for (int i = threadIdx.x; i < N; i += NT) out[off + i] = buf[i];
 }
 

@@ -298,7 +298,7 @@ def test_nonsquare_image():
 
 
 # ---------------------------------------------------------------- fused step and graphs
-@pytest.mark.parametrize("dtype,width", [(T.C64, 7), (T.C128, 14)])
+@pytest.mark.parametrize("dtype,width", [(T.C64, 7), (T.C128, 14), (T.C64_FP16IN, 7)])
 def test_entropy_step_matches_separate_calls_and_oracle(dtype, width):
     print(f"entropy step dtype={dtype}", flush=True)
     case = Case(48, 160, 96, fov=60.0, dtype=dtype, width=width, seed=21)
