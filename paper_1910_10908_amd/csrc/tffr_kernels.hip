@@ -268,9 +268,10 @@ __device__ __forceinline__ void fft_from(cplx<R>* buf, const cplx<R>* tw) {
 // Stages of radix MAXRAD (8 or 16) and one smaller last stage.  Radix 16 takes fewer LDS
 // passes and, in the dense-slice range kernel, fewer registers (more workgroups per CU);
 // radix 8 keeps more threads busy per stage where a workgroup has few butterflies.
-// SWZ: values between stages in the bank-spreading layout (swz).  It pays in the
-// one-transform range kernels; in the batched azimuth transforms the per-element
-// addresses cost more registers than the conflicts cost time.
+// SWZ: values between stages in the bank-spreading layout (swz).  Used wherever a
+// thread takes one butterfly per stage; with two or more (the entropy step's and the
+// coordinate gradient's two-field adjoint transforms) the per-element addresses cost
+// more registers than the conflicts cost time.
 template <int SIGN, int N, int NT, int NBAT = 1, int MAXRAD = 8, bool SWZ = false, typename R>
 __device__ __forceinline__ void lds_fft(cplx<R>* buf, const cplx<R>* tw) {
   fft_from<SIGN, N, 1, NT, NBAT, MAXRAD, SWZ>(buf, tw);
@@ -931,7 +932,7 @@ __global__ __launch_bounds__(NT) void k_fwd_cols(Geo g, Tab<R> t, const cplx<R>*
   __syncthreads();
   cols_gather<R, N, NT, CB>(g, t, ce, hs, buf);
   __syncthreads();
-  lds_fft<+1, N, NT, CB>(buf, tw);
+  lds_fft<+1, N, NT, CB, 8, true>(buf, tw);
   double es = 0.0, et = 0.0;
 #pragma unroll
   for (int c = 0; c < CB; ++c) {
@@ -1005,7 +1006,7 @@ __global__ __launch_bounds__(NT) void k_ent_cols(Geo g, Tab<R> t, const cplx<R>*
   __syncthreads();
   cols_gather<R, N, NT, CB>(g, t, ce, hs, buf);
   __syncthreads();
-  lds_fft<+1, N, NT, CB>(buf, tw);
+  lds_fft<+1, N, NT, CB, 8, true>(buf, tw);
   // image pixels: thread owns fine bins i = threadIdx.x + j NT (pixel jy = signed(i) + my/2)
   double es = 0.0, et = 0.0;
   cplx<R> v[CB][DPT];
@@ -1132,7 +1133,7 @@ __global__ __launch_bounds__(NT) void k_adj_cols(Geo g, Tab<R> t, const cplx<R>*
   }
   __syncthreads();
   const SliceTaps<R> first = load_first_slice(g, t);
-  lds_fft<-1, N, NT, CB>(buf, tw);
+  lds_fft<-1, N, NT, CB, 8, true>(buf, tw);
   cplx<R>* outs[1] = {hx};
   cols_interp<R, N, NT, CB, CB>(g, t, buf, ncol, outs, c0, first);
 }
