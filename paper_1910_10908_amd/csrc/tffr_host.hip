@@ -190,7 +190,9 @@ int sample_type(const tffr_plan* P) {
 
 // Piecewise polynomial of 1/g(delta) on (0, 1) for the FP32 path: nseg segments, local
 // variable t in [-1, 1], monomial coefficients (highest first) from interpolation at
-// Chebyshev points.  Returns false when the fit misses 2e-8 relative somewhere.
+// Chebyshev points, stored coefficient-major (out[j * nseg + s]: lanes evaluating
+// different segments read consecutive words, so distinct LDS banks).  Returns false
+// when the fit misses 2e-8 relative somewhere.
 bool fit_weight_poly(double a, double q, int nseg, int deg, std::vector<float>& out) {
   out.assign((size_t)nseg * (deg + 1), 0.0f);
   const int np = deg + 1;
@@ -221,7 +223,7 @@ bool fit_weight_poly(double a, double q, int nseg, int deg, std::vector<float>& 
       for (int j = r + 1; j < np; ++j) v -= M[(size_t)r * np + j] * c[j];
       c[r] = v / M[(size_t)r * np + r];
     }
-    for (int j = 0; j < np; ++j) out[(size_t)s * np + j] = (float)c[j];
+    for (int j = 0; j < np; ++j) out[(size_t)j * nseg + s] = (float)c[j];
     for (int i = 0; i <= 32; ++i) {
       const double t = -1.0 + i / 16.0, delta = (s + 0.5 * (t + 1.0)) / nseg;
       if (delta <= 0.0 || delta >= 1.0) continue;
@@ -662,8 +664,8 @@ tffr_status plan_create(const tffr_params* p, const double* k, const double* ku,
 
   // tFFR weight polynomial (float path, integer q only: the tap set is then constant on (0, 1))
   g.use_poly = 0;
-  g.nseg = 32;
-  g.deg = 7;
+  g.nseg = tffr::kPolySeg;
+  g.deg = tffr::kPolyDeg;
   if (!P->dbl() && p->weighting == TFFR_W_TFFR && std::fabs(p->q - std::round(p->q)) < 1e-12) {
     std::vector<float> poly;
     if (fit_weight_poly(p->window_a, p->q, g.nseg, g.deg, poly)) {

@@ -58,7 +58,7 @@ struct Tab {
   const cplx<R>* twy;     // [nfy/64 + 64] two-level table of exp(+2 pi i m / nfy)
   const int32_t* ycell_n;  // [nfy][yemax] slices whose taps reach each azimuth cell (padded with 0)
   const R* ycell_w;        // [nfy][yemax] the matching kernel taps (padded with 0)
-  const float* poly;      // [nseg][deg+1] tFFR weight polynomial (float path), or null
+  const float* poly;      // [kPolyDeg+1][kPolySeg] tFFR weight polynomial (float path), or null
 };
 
 enum SampleType { ST_C64 = 0, ST_C128 = 1, ST_H2 = 2 };
@@ -123,6 +123,8 @@ hipError_t launch_fft(int log2n, int batch, int sign, int max_radix, const cplx<
 
 size_t max_dynamic_lds();  // bytes of LDS one workgroup may use on this device
 int rows_threads(int logn);  // threads per workgroup of the range-stage kernels for a 2^logn fine row
+constexpr int kPolySeg = 32;  // segments of the tFFR weight polynomial on (0, 1)
+constexpr int kPolyDeg = 7;   // degree per segment
 constexpr int kRunWindow = 8;  // register window of the sliding-window range kernel (widths up to 8)
 
 }  // namespace tffr

@@ -338,11 +338,9 @@ __device__ __attribute__((noinline)) double tffr_weight_f64(double delta, double
   return keep ? inv : 0.0;
 }
 
-constexpr int kPolySeg = 32;  // segments of the tFFR weight polynomial on (0, 1)
-constexpr int kPolyDeg = 7;   // degree per segment
-
 // tFFR weight R_tau(1/g) of a sample at lattice coordinate lam; poly is the piecewise
-// polynomial of 1/g in the local variable of each segment (LDS copy on the float path).
+// polynomial of 1/g in the local variable of each segment, coefficient-major
+// (poly[i * kPolySeg + seg]; LDS copy on the float path).
 template <typename R>
 __device__ __forceinline__ R tffr_weight(const Geo& g, const float* poly, double lam) {
   const double delta = lam - floor(lam);
@@ -351,10 +349,10 @@ __device__ __forceinline__ R tffr_weight(const Geo& g, const float* poly, double
     const double xs = delta * kPolySeg;
     const int seg = min((int)xs, kPolySeg - 1);
     const float t = (float)(2.0 * (xs - seg) - 1.0);
-    const float* c = poly + seg * (kPolyDeg + 1);
+    const float* c = poly + seg;
     float v = c[0];
 #pragma unroll
-    for (int i = 1; i <= kPolyDeg; ++i) v = fmaf(v, t, c[i]);
+    for (int i = 1; i <= kPolyDeg; ++i) v = fmaf(v, t, c[i * kPolySeg]);
     const float thr = g.thr_f;
     if (fabsf(v - thr) > g.near_f * thr) {
       const bool keep = g.thresh_mode == 0 ? (v >= thr) : (v <= thr);
