@@ -253,11 +253,13 @@ __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* tw) {
   __syncthreads();
 }
 
-template <int SIGN, int N, int P, int NT, int NBAT, int MAXRAD, bool SWZ, typename R>
+template <int SIGN, int N, int P, int NT, int NBAT, int MAXRAD, int SWZ, typename R>
 __device__ __forceinline__ void fft_from(cplx<R>* buf, const cplx<R>* tw) {
   if constexpr (P < N) {
     constexpr int RAD = (N / P) >= MAXRAD ? MAXRAD : (N / P);
-    fft_stage<SIGN, N, RAD, P, NT, NBAT, SWZ && (P > 1), SWZ && (P * RAD < N)>(buf, tw);
+    constexpr bool in = P > 1 && (SWZ == 1 || (SWZ == 2 && P == MAXRAD));
+    constexpr bool out = P * RAD < N && (SWZ == 1 || (SWZ == 2 && P == 1));
+    fft_stage<SIGN, N, RAD, P, NT, NBAT, in, out>(buf, tw);
     fft_from<SIGN, N, P * RAD, NT, NBAT, MAXRAD, SWZ>(buf, tw);
   }
 }
@@ -268,11 +270,12 @@ __device__ __forceinline__ void fft_from(cplx<R>* buf, const cplx<R>* tw) {
 // Stages of radix MAXRAD (8 or 16) and one smaller last stage.  Radix 16 takes fewer LDS
 // passes and, in the dense-slice range kernel, fewer registers (more workgroups per CU);
 // radix 8 keeps more threads busy per stage where a workgroup has few butterflies.
-// SWZ: values between stages in the bank-spreading layout (swz).  Used wherever a
-// thread takes one butterfly per stage; with two or more (the entropy step's and the
-// coordinate gradient's two-field adjoint transforms) the per-element addresses cost
-// more registers than the conflicts cost time.
-template <int SIGN, int N, int NT, int NBAT = 1, int MAXRAD = 8, bool SWZ = false, typename R>
+// SWZ: 0 plain layout; 1 every value between stages in the bank-spreading layout
+// (swz); 2 only the first stage's output (its stride-RAD stores conflict most).  Mode 1
+// where a thread takes one butterfly per stage; with two (the entropy step's two-field
+// adjoint transforms) the per-element addresses of mode 1 cost more registers than the
+// conflicts cost time, mode 2 fits.
+template <int SIGN, int N, int NT, int NBAT = 1, int MAXRAD = 8, int SWZ = 0, typename R>
 __device__ __forceinline__ void lds_fft(cplx<R>* buf, const cplx<R>* tw) {
   fft_from<SIGN, N, 1, NT, NBAT, MAXRAD, SWZ>(buf, tw);
 }
@@ -613,7 +616,7 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(Geo g, Tab<R> t, int stype, con
     const int jx = threadIdx.x + j * NT;
     dx[j] = jx < mx ? t.deapx[jx] : (R)0;
   }
-  lds_fft<+1, N, NT, 1, 8, true>(buf, tw);
+  lds_fft<+1, N, NT, 1, 8, 1>(buf, tw);
 #pragma unroll
   for (int j = 0; j < DPT; ++j) {
     const int jx = threadIdx.x + j * NT;
@@ -732,7 +735,7 @@ __global__ __launch_bounds__(NT) void k_fwd_rows_run(Geo g, Tab<R> t, int stype,
     const int jx = threadIdx.x + j * NT;
     dx[j] = jx < mx ? t.deapx[jx] : (R)0;
   }
-  lds_fft<+1, N, NT, 1, 16, true>(buf, tw);
+  lds_fft<+1, N, NT, 1, 16, 1>(buf, tw);
 #pragma unroll
   for (int j = 0; j < DPT; ++j) {
     const int jx = threadIdx.x + j * NT;
@@ -930,7 +933,7 @@ __global__ __launch_bounds__(NT) void k_fwd_cols(Geo g, Tab<R> t, const cplx<R>*
   __syncthreads();
   cols_gather<R, N, NT, CB>(g, t, ce, hs, buf);
   __syncthreads();
-  lds_fft<+1, N, NT, CB, 8, true>(buf, tw);
+  lds_fft<+1, N, NT, CB, 8, 1>(buf, tw);
   double es = 0.0, et = 0.0;
 #pragma unroll
   for (int c = 0; c < CB; ++c) {
@@ -1004,7 +1007,7 @@ __global__ __launch_bounds__(NT) void k_ent_cols(Geo g, Tab<R> t, const cplx<R>*
   __syncthreads();
   cols_gather<R, N, NT, CB>(g, t, ce, hs, buf);
   __syncthreads();
-  lds_fft<+1, N, NT, CB, 8, true>(buf, tw);
+  lds_fft<+1, N, NT, CB, 8, 1>(buf, tw);
   // image pixels: thread owns fine bins i = threadIdx.x + j NT (pixel jy = signed(i) + my/2)
   double es = 0.0, et = 0.0;
   cplx<R> v[CB][DPT];
@@ -1051,7 +1054,7 @@ __global__ __launch_bounds__(NT) void k_ent_cols(Geo g, Tab<R> t, const cplx<R>*
     }
   }
   __syncthreads();
-  lds_fft<-1, N, NT, 2 * CB>(buf, tw);  // buf and hs are contiguous: 2 CB columns
+  lds_fft<-1, N, NT, 2 * CB, 8, 2>(buf, tw);  // buf and hs are contiguous: 2 CB columns
   cplx<R>* outs[1] = {h12};
   cols_interp<R, N, NT, 2 * CB, CB, true>(g, t, buf, ncol, outs, c0, first);
 }
@@ -1131,7 +1134,7 @@ __global__ __launch_bounds__(NT) void k_adj_cols(Geo g, Tab<R> t, const cplx<R>*
   }
   __syncthreads();
   const SliceTaps<R> first = load_first_slice(g, t);
-  lds_fft<-1, N, NT, CB, 8, true>(buf, tw);
+  lds_fft<-1, N, NT, CB, 8, 1>(buf, tw);
   cplx<R>* outs[1] = {hx};
   cols_interp<R, N, NT, CB, CB>(g, t, buf, ncol, outs, c0, first);
 }
@@ -1206,7 +1209,7 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
   const double ku = t.ku[n];
   const R halfw = (R)(0.5 * g.W), inv_halfw = (R)(2.0 / g.W), beta = es_shape<R>(g);
   __syncthreads();
-  lds_fft<-1, N, NT, 1, 8, true>(buf, tw);
+  lds_fft<-1, N, NT, 1, 8, 1>(buf, tw);
   double acc_phase = 0.0;
   for (int p = threadIdx.x; p < g.n_freq; p += NT) {
     const double kp = k_next;
@@ -1655,7 +1658,7 @@ __global__ __launch_bounds__(NT) void k_fft(const cplx<R>* __restrict__ in, cplx
   load_twiddles<N, NT>(twl, tw);
   for (int i = threadIdx.x; i < N; i += NT) buf[i] = in[off + i];
   __syncthreads();
-  lds_fft<SIGN, N, NT, 1, MAXRAD, true>(buf, twl);
+  lds_fft<SIGN, N, NT, 1, MAXRAD, 1>(buf, twl);
   for (int i = threadIdx.x; i < N; i += NT) out[off + i] = buf[i];
 }
 
