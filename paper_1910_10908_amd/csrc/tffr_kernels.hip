@@ -770,10 +770,27 @@ struct alignas(CB * sizeof(cplx<R>) >= 16 ? 16 : CB * sizeof(cplx<R>)) CVec {
 
 // Stage the block's CB columns of the range spectra in LDS as hs[n][c] (zeros past the
 // last column of the image).  A slice's CB values are one wide load when the block is
-// full and the rows keep CB-alignment.
+// full and the rows keep CB-alignment.  With one column per block (the largest images,
+// several slices per thread) each slice is a separate row of the spectra, so a thread
+// issues four slices' loads before storing any: one latency per batch, not per slice.
 template <typename R, int NT, int CB>
 __device__ __forceinline__ void stage_spectra(const Geo& g, const cplx<R>* __restrict__ hx, cplx<R>* hs, int c0,
                                               int ncol) {
+  if constexpr (CB == 1) {
+    constexpr int SU = 4;
+    for (int n0 = threadIdx.x; n0 < g.n_pulses; n0 += SU * NT) {
+      cplx<R> v[SU];
+#pragma unroll
+      for (int u = 0; u < SU; ++u) {
+        const int nn = n0 + u * NT;
+        v[u] = nn < g.n_pulses ? hx[(size_t)nn * g.mx + c0] : cplx<R>{0, 0};
+      }
+#pragma unroll
+      for (int u = 0; u < SU; ++u)
+        if (n0 + u * NT < g.n_pulses) hs[n0 + u * NT] = v[u];
+    }
+    return;
+  }
   if (CB > 1 && ncol == CB && g.mx % CB == 0) {
     for (int nn = threadIdx.x; nn < g.n_pulses; nn += NT)
       *reinterpret_cast<CVec<R, CB>*>(hs + nn * CB) =
@@ -827,13 +844,16 @@ struct SliceTaps {
   R tap[kRunWindow];
 };
 template <typename R>
-__device__ __forceinline__ SliceTaps<R> load_first_slice(const Geo& g, const Tab<R>& t) {
+__device__ __forceinline__ SliceTaps<R> load_slice(const Geo& g, const Tab<R>& t, int nn) {
   SliceTaps<R> f;
-  const int nn = min((int)threadIdx.x, g.n_pulses - 1);
   f.ys = t.ystart[nn];
 #pragma unroll
   for (int i = 0; i < kRunWindow; ++i) f.tap[i] = i < g.W ? t.ytap[(size_t)nn * g.W + i] : (R)0;
   return f;
+}
+template <typename R>
+__device__ __forceinline__ SliceTaps<R> load_first_slice(const Geo& g, const Tab<R>& t) {
+  return load_slice(g, t, min((int)threadIdx.x, g.n_pulses - 1));
 }
 
 // IL (interleaved, NC = 2 CS): a single output array [n_pulses][mx][2] takes column
