@@ -994,8 +994,9 @@ __global__ __launch_bounds__(NT) void k_fwd_cols(Geo g, Tab<R> t, const cplx<R>*
 // transform of both fields, I (ln|I|^2 - cc) -> h1 and I -> h2, with cc = ln of the
 // block's mean |I|^2 (keeps the first field centred; stored in cblk), and the range
 // adjoint combines alpha h1 + (beta + alpha cc) h2 once the global sums are known.
-// LDS: the two fields' fine columns [2][CB][N] reuse the staged-spectra space.  h1 may
-// be hx itself: a block reads only its own columns of hx, all before its first write.
+// LDS: the two fields' fine columns [2][CB][N] reuse the staged-spectra space.  h12 is
+// [n_pulses][mx][2]: h1 and h2 of each image column interleaved, so a slice's values of
+// the block are one contiguous store.
 template <typename R, int LOGN, int NT, int CB>
 __global__ __launch_bounds__(NT) void k_ent_cols(Geo g, Tab<R> t, const cplx<R>* __restrict__ hx,
                                                  cplx<R>* __restrict__ img, double* __restrict__ partials,
