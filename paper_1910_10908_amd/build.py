@@ -1,15 +1,19 @@
-"""Build libtffr.so (HIP, gfx950) in-tree with hipcc."""
+"""Build libtffr.so (HIP, gfx950) in-tree with hipcc (one object per source, compiled in
+parallel, then linked)."""
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libtffr.so")
-SOURCES = ["tffr_host.hip", "tffr_kernels.hip"]
+SOURCES = ["tffr_host.hip"]
+# kernel sources: one object per compute type (FP32 / FP64 instantiations), built in parallel
+KERNEL_SOURCES = ["tffr_range.hip", "tffr_azimuth.hip", "tffr_entstep.hip", "tffr_coord.hip", "tffr_misc.hip"]
 ARCH = "gfx950"
 
 
@@ -29,13 +33,21 @@ def build(verbose=False):
              "-I", INCLUDE, "-I", CSRC]
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    for src in SOURCES:
-        obj = os.path.join(bdir, src.replace(".hip", ".o"))
-        cmd = [hipcc()] + flags + ["-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+    cmds = []
+    jobs = [(src, src.replace(".hip", ".o"), []) for src in SOURCES]
+    for src in KERNEL_SOURCES:
+        for tag, define in (("f32", "TFFR_REAL_F32"), ("f64", "TFFR_REAL_F64")):
+            jobs.append((src, src.replace(".hip", f"_{tag}.o"), ["-D" + define]))
+    for src, oname, extra in jobs:
+        obj = os.path.join(bdir, oname)
+        cmds.append([hipcc()] + flags + extra + ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+        if verbose:
+            print(" ".join(cmds[-1]), flush=True)
+    with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as ex:
+        for r in list(ex.map(lambda c: subprocess.run(c), cmds)):
+            if r.returncode != 0:
+                raise subprocess.CalledProcessError(r.returncode, r.args)
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

@@ -1,5 +1,5 @@
-// Internal types shared by the host plan (tffr_host.hip) and the kernels
-// (tffr_kernels.hip).  Nothing here crosses the public C ABI.
+// Internal types shared by the host plan (tffr_host.hip) and the kernel sources
+// (tffr_range.hip, tffr_azimuth.hip, tffr_misc.hip).  Nothing here crosses the public C ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -79,7 +79,7 @@ struct EntComb {
   double* loss;
 };
 
-// Launchers (tffr_kernels.hip).  All enqueue on `st` and return the launch status.
+// Launchers (tffr_range.hip, tffr_azimuth.hip, tffr_misc.hip).  All enqueue on `st` and return the launch status.
 template <typename R>
 hipError_t launch_fwd_rows(const Geo& g, const Tab<R>& t, int stype, const void* samples,
                            const R* phase, const R* dalong, const R* w, cplx<R>* out,
@@ -100,6 +100,9 @@ hipError_t launch_adj_rows(const Geo& g, const Tab<R>& t, int stype, const cplx<
                            const void* samples, const R* phase, const R* dalong, const R* w,
                            cplx<R>* grad_s, R* grad_phase, R* grad_dalong, const EntComb<R>& ec,
                            hipStream_t st);
+template <typename R>
+hipError_t launch_coord_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>* cot, cplx<R>* h0, cplx<R>* h1,
+                             hipStream_t st);
 template <typename R>
 hipError_t launch_coord_grad(const Geo& g, const Tab<R>& t, int cb, int stype, const cplx<R>* cot,
                              const void* samples, const R* phase, const R* dalong, const R* w, cplx<R>* h0,

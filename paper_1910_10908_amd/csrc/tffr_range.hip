@@ -1,0 +1,429 @@
+// Range-stage kernels of libtffr: type-1 gridding of each azimuth slice with the fused
+// coordinate prep and weights (sub-pass and sliding-window variants), and the type-2
+// range adjoint with the per-slice phase / position gradient reduction.
+
+#include "tffr_device.h"
+
+namespace tffr {
+
+// ============================================================================ forward
+// Range stage: one azimuth slice per workgroup.  Spread the slice's weighted samples
+// onto the periodic fine row, inverse FFT, keep the centred mx bins and divide by the
+// kernel transform.  stage 0 dumps the gridded row instead.
+//
+// No atomics: kx grows along a slice, so when thread t takes the sample
+// p = part start + block * S * NT + S t + j in sub-pass j, the samples of one sub-pass
+// are S apart and their cell ranges are disjoint (the plan picks S with
+// S * (smallest sample spacing) > W).  The slice is cut into parts whose span is less
+// than the fine row, so no two samples of a part meet after wrapping.  Each sub-pass is
+// a plain read-add-write into LDS followed by a barrier; the raw inputs of the next
+// sub-pass are loaded while the current one is processed.
+template <typename R, int LOGN, int NT, int SG>
+__global__ __launch_bounds__(NT) void k_fwd_rows(Geo g, Tab<R> t, int stype, const void* __restrict__ samples,
+                                                 const R* __restrict__ phase, const R* __restrict__ dalong,
+                                                 const R* __restrict__ w, cplx<R>* __restrict__ out, int stage) {
+  constexpr int N = 1 << LOGN;
+  constexpr int DPT = (N + NT - 1) / NT;  // >= output bins per thread (mx <= N)
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
+  cplx<R>* buf = tw + tw_entries<N>();
+  float* lpoly = reinterpret_cast<float*>(buf + N);
+  const int n = blockIdx.x;
+  const bool ffr = g.weighting == 2;
+  const int S = g.sub, W = g.W, plen = g.part_len;
+  const int nblk = (plen + S * NT - 1) / (S * NT);
+  const size_t base = (size_t)n * g.n_freq;
+  load_twiddles<N, NT>(tw, t.twx);
+  const float* poly = load_poly<NT>(g, t.poly, lpoly);
+  for (int i = threadIdx.x; i < N; i += NT) buf[i] = {0, 0};
+  const cplx<R> rot = row_rotation(t, phase, dalong, n);
+  const double ku = t.ku[n];
+  const R halfw = (R)(0.5 * g.W), inv_halfw = (R)(2.0 / g.W), beta = es_shape<R>(g);
+  bool first = true;
+  for (int pa = 0; pa < g.n_freq; pa += plen) {
+    const int pb = min(pa + plen, g.n_freq);
+    for (int blk = 0; blk < nblk; ++blk) {
+      const int p0 = pa + blk * S * NT + S * (int)threadIdx.x;  // this thread's S consecutive samples
+      for (int j0 = 0; j0 < S; j0 += SG) {
+        // raw inputs of up to SG consecutive samples, loaded back to back
+        double kr[SG];
+        cplx<R> sr[SG];
+#pragma unroll
+        for (int j = 0; j < SG; ++j) {
+          const int p = p0 + j0 + j;
+          const bool ok = j0 + j < S && p < pb;
+          kr[j] = ok ? raw_k(t, g.n_freq, n, p) : 0.0;
+          sr[j] = (ok && !ffr) ? load_sample<R>(samples, stype, base + p) : cplx<R>{0, 0};
+        }
+        if (first) {
+          __syncthreads();  // row zeroed, tables in LDS
+          first = false;
+        }
+#pragma unroll
+        for (int j = 0; j < SG; ++j) {
+          if (j0 + j < S) {
+            const int p = p0 + j0 + j;
+            if (p < pb) {
+              const double kx = kx_of(t, kr[j], ku);
+              const double lam = lattice_coord(kx, g);
+              const cplx<R> c = weighted_sample<R>(g, t, poly, stype, samples, w, n, p, ku, lam, rot, sr[j]);
+              if (g.literal) {
+                lit_spread<R>(buf, N, kx * g.tx_scale, g.q, g.lit_taps, g.a, g.ema2, c);
+              } else {
+                int ui;
+                R f;
+                fine_pos<R>(kx * g.tx_scale, N, ui, f);
+                const int k0 = (int)ceil(f - halfw);
+                const int cell = ui + k0;
+                const R z0 = ((R)k0 - f) * inv_halfw;
+                for (int i = 0; i < W; ++i) {
+                  const R phi = es_kernel(z0 + (R)i * inv_halfw, beta);
+                  cplx<R>& bb = buf[(cell + i) & (N - 1)];
+                  bb = bb + phi * c;
+                }
+              }
+            }
+            __syncthreads();
+          }
+        }
+      }
+    }
+  }
+  if (first) __syncthreads();
+  if (stage == 0) {
+    for (int i = threadIdx.x; i < N; i += NT) out[(size_t)n * N + i] = buf[i];
+    return;
+  }
+  const int mx = g.mx;
+  R dx[DPT];
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) {
+    const int jx = threadIdx.x + j * NT;
+    dx[j] = jx < mx ? t.deapx[jx] : (R)0;
+  }
+  lds_fft<+1, N, NT, 1, 8, 1>(buf, tw);
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) {
+    const int jx = threadIdx.x + j * NT;
+    if (jx < mx) out[(size_t)n * mx + jx] = dx[j] * buf[(jx - mx / 2) & (N - 1)];
+  }
+}
+
+// Range stage for densely sampled slices (the plan's choice when consecutive samples sit
+// well under W fine cells apart).  Thread t takes the run of S consecutive samples
+// p0 = part start + S t ... and slides a window of W register accumulators along the
+// fine row: a sample whose first tap cell is c0 first retires the window cells below c0
+// (in increasing cell order), then adds its W taps to the window at fixed register
+// positions.  With S * (smallest sample spacing) > W, the first W cells a run retires
+// (its "lead") are the only cells another run (the previous one) also reaches, so
+// every other retired cell is read-add-written into LDS at once without conflict; the
+// lead cells are kept in registers and added after one barrier, when no other run
+// writes.  Two barriers per part instead of one per sample of a run.
+template <typename R, int LOGN, int NT, int WM>
+__global__ __launch_bounds__(NT) void k_fwd_rows_run(Geo g, Tab<R> t, int stype, const void* __restrict__ samples,
+                                                     const R* __restrict__ phase, const R* __restrict__ dalong,
+                                                     const R* __restrict__ w, cplx<R>* __restrict__ out,
+                                                     int stage) {
+  constexpr int N = 1 << LOGN;
+  constexpr int DPT = (N + NT - 1) / NT;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
+  cplx<R>* buf = tw + tw_entries<N>();
+  float* lpoly = reinterpret_cast<float*>(buf + N);
+  const int n = blockIdx.x;
+  const bool ffr = g.weighting == 2;
+  const int S = g.sub, W = g.W, plen = g.part_len;
+  const size_t base_s = (size_t)n * g.n_freq;
+  load_twiddles<N, NT>(tw, t.twx);
+  const float* poly = load_poly<NT>(g, t.poly, lpoly);
+  for (int i = threadIdx.x; i < N; i += NT) buf[i] = {0, 0};
+  const cplx<R> rot = row_rotation(t, phase, dalong, n);
+  const double ku = t.ku[n];
+  const R halfw = (R)(0.5 * g.W), inv_halfw = (R)(2.0 / g.W), beta = es_shape<R>(g);
+  __syncthreads();  // row zeroed, tables in LDS
+  for (int pa = 0; pa < g.n_freq; pa += plen) {
+    const int pb = min(pa + plen, g.n_freq);
+    const int p0 = pa + S * (int)threadIdx.x;
+    const int p1 = min(p0 + S, pb);
+    cplx<R> acc[WM], lead[WM];
+#pragma unroll
+    for (int i = 0; i < WM; ++i) acc[i] = lead[i] = cplx<R>{0, 0};
+    int base = 0, cfirst = 0;
+    // retire the lowest window cell: into the lead registers if it is one of the run's
+    // first W cells, else straight into the row; then shift the window down one cell
+    auto retire = [&]() {
+      if (base - cfirst < W) {
+#pragma unroll
+        for (int i = 0; i + 1 < WM; ++i) lead[i] = lead[i + 1];
+        lead[WM - 1] = acc[0];
+      } else {
+        cplx<R>& bb = buf[base & (N - 1)];
+        bb = bb + acc[0];
+      }
+#pragma unroll
+      for (int i = 0; i + 1 < WM; ++i) acc[i] = acc[i + 1];
+      acc[WM - 1] = cplx<R>{0, 0};
+      ++base;
+    };
+    double k_nx = p0 < p1 ? raw_k(t, g.n_freq, n, p0) : 0.0;
+    cplx<R> s_nx = (p0 < p1 && !ffr) ? load_sample<R>(samples, stype, base_s + p0) : cplx<R>{0, 0};
+    for (int p = p0; p < p1; ++p) {
+      const double kp = k_nx;
+      const cplx<R> sp = s_nx;
+      if (p + 1 < p1) {
+        k_nx = raw_k(t, g.n_freq, n, p + 1);
+        if (!ffr) s_nx = load_sample<R>(samples, stype, base_s + p + 1);
+      }
+      const double kx = kx_of(t, kp, ku);
+      const double lam = lattice_coord(kx, g);
+      const cplx<R> c = weighted_sample<R>(g, t, poly, stype, samples, w, n, p, ku, lam, rot, sp);
+      const double tt = kx * g.tx_scale;
+      int ui;
+      R f;
+      fine_pos<R>(tt, N, ui, f);
+      const int k0 = (int)ceil(f - halfw);
+      // unwrapped first tap cell (only differences and the low LOGN bits are used)
+      const int c0 = (int)((unsigned)(int)floor(tt) * (unsigned)N + (unsigned)(ui + k0));
+      if (p == p0) base = cfirst = c0;
+      for (int adv = c0 - base; adv > 0; --adv) retire();
+      const R z0 = ((R)k0 - f) * inv_halfw;
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        if (i < W) {
+          const R phi = es_kernel(z0 + (R)i * inv_halfw, beta);
+          acc[i] = acc[i] + phi * c;
+        }
+      }
+    }
+    if (p0 < p1)
+      for (int i = 0; i < W; ++i) retire();
+    __syncthreads();
+    if (p0 < p1) {
+#pragma unroll
+      for (int i = 0; i < WM; ++i) {
+        if (i >= WM - W) {
+          cplx<R>& bb = buf[(cfirst + i - (WM - W)) & (N - 1)];
+          bb = bb + lead[i];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (stage == 0) {
+    for (int i = threadIdx.x; i < N; i += NT) out[(size_t)n * N + i] = buf[i];
+    return;
+  }
+  const int mx = g.mx;
+  R dx[DPT];
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) {
+    const int jx = threadIdx.x + j * NT;
+    dx[j] = jx < mx ? t.deapx[jx] : (R)0;
+  }
+  lds_fft<+1, N, NT, 1, 16, 1>(buf, tw);
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) {
+    const int jx = threadIdx.x + j * NT;
+    if (jx < mx) out[(size_t)n * mx + jx] = dx[j] * buf[(jx - mx / 2) & (N - 1)];
+  }
+}
+
+// Range stage, type 2: per slice, divide by the kernel transform, zero-pad, forward FFT
+// (sign -), interpolate at every sample, apply D^T and exp(-i psi), and reduce the
+// per-slice phase gradient sum_p Re(conj(g'_p) i s'_p) = sum_p (g_i s_r - g_r s_i).
+// The raw inputs of a thread's first sample are loaded before the FFT, and those of
+// the next sample while the current one is processed.
+template <typename R, int LOGN, int NT>
+__global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, const cplx<R>* __restrict__ hx,
+                                                 const void* __restrict__ samples, const R* __restrict__ phase,
+                                                 const R* __restrict__ dalong, const R* __restrict__ w,
+                                                 cplx<R>* __restrict__ grad_s, R* __restrict__ grad_phase,
+                                                 R* __restrict__ grad_dalong, EntComb<R> ec) {
+  constexpr int N = 1 << LOGN;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
+  cplx<R>* buf = tw + tw_entries<N>();
+  float* lpoly = reinterpret_cast<float*>(buf + N);
+  cplx<R>* gbuf = reinterpret_cast<cplx<R>*>(lpoly + kPolyLds);  // FFR only: interpolated values
+  const int n = blockIdx.x;
+  const int mx = g.mx;
+  const size_t base = (size_t)n * g.n_freq;
+  const bool ffr = g.weighting == 2;
+  const bool want_phase = grad_phase || grad_dalong;
+  const bool need_s = want_phase && !ffr;
+  int p_next = threadIdx.x;
+  double k_next = p_next < g.n_freq ? raw_k(t, g.n_freq, n, p_next) : 0.0;
+  cplx<R> s_next = (need_s && p_next < g.n_freq) ? load_sample<R>(samples, stype, base + p_next) : cplx<R>{0, 0};
+  R w_next = (w && !ffr && p_next < g.n_freq) ? w[base + p_next] : (R)0;
+  load_twiddles<N, NT>(tw, t.twx);
+  const float* poly = load_poly<NT>(g, t.poly, lpoly);
+  const cplx<R>* in = hx + (size_t)n * mx;
+  if (ec.h12) {
+    // entropy step: the range-spectra cotangent is alpha h1 + (beta + alpha cc[col block]) h2
+    double S, T;
+    if (ec.partials) {
+      double es = 0.0, et = 0.0;
+      for (int i = threadIdx.x; i < ec.nparts; i += NT) {
+        es += ec.partials[2 * i];
+        et += ec.partials[2 * i + 1];
+      }
+      S = block_sum<NT>(es);
+      T = block_sum<NT>(et);
+      if (ec.loss && n == 0 && threadIdx.x == 0) *ec.loss = S > 0.0 ? log(S) - T / S : 0.0;
+    } else {
+      S = ec.stats[0];
+      T = S > 0.0 ? S * (log(S) - ec.stats[1]) : 0.0;
+    }
+    const double al = S > 0.0 ? -2.0 / S : 0.0, be = S > 0.0 ? 2.0 * T / (S * S) : 0.0;
+    const CVec<R, 2>* in12 = reinterpret_cast<const CVec<R, 2>*>(ec.h12) + (size_t)n * mx;
+    for (int i = threadIdx.x; i < N; i += NT) {
+      const int jp = i < N / 2 ? i : i - N;
+      const int jx = jp + mx / 2;
+      cplx<R> v = {0, 0};
+      if (jx >= 0 && jx < mx) {
+        const R c2 = (R)(be + al * (double)ec.cblk[jx / ec.cb]);
+        const CVec<R, 2> f = in12[jx];
+        v = t.deapx[jx] * ((R)al * f.v[0] + c2 * f.v[1]);
+      }
+      buf[i] = v;
+    }
+  } else {
+    for (int i = threadIdx.x; i < N; i += NT) {
+      const int jp = i < N / 2 ? i : i - N;
+      const int jx = jp + mx / 2;
+      buf[i] = (jx >= 0 && jx < mx) ? t.deapx[jx] * in[jx] : cplx<R>{0, 0};
+    }
+  }
+  const cplx<R> rot = row_rotation(t, phase, dalong, n);
+  const double ku = t.ku[n];
+  const R halfw = (R)(0.5 * g.W), inv_halfw = (R)(2.0 / g.W), beta = es_shape<R>(g);
+  __syncthreads();
+  lds_fft<-1, N, NT, 1, 8, 1>(buf, tw);
+  double acc_phase = 0.0;
+  for (int p = threadIdx.x; p < g.n_freq; p += NT) {
+    const double kp = k_next;
+    const cplx<R> sp = s_next;
+    const R wp = w_next;
+    p_next = p + NT;
+    if (p_next < g.n_freq) {
+      k_next = raw_k(t, g.n_freq, n, p_next);
+      if (need_s) s_next = load_sample<R>(samples, stype, base + p_next);
+      if (w && !ffr) w_next = w[base + p_next];
+    }
+    const double kx = kx_of(t, kp, ku);
+    cplx<R> a = {0, 0};
+    if (g.literal) {
+      a = lit_gather<R>(buf, N, kx * g.tx_scale, g.q, g.lit_taps, g.a, g.ema2);
+    } else {
+      int ui;
+      R f;
+      fine_pos<R>(kx * g.tx_scale, N, ui, f);
+      const int k0 = (int)ceil(f - halfw);
+      const int cell = ui + k0;
+      const R z0 = ((R)k0 - f) * inv_halfw;
+      for (int i = 0; i < g.W; ++i) {
+        const R phi = es_kernel(z0 + (R)i * inv_halfw, beta);
+        a = a + phi * buf[(cell + i) & (N - 1)];
+      }
+    }
+    if (ffr) {
+      gbuf[p] = a;
+      continue;
+    }
+    const R wt = w ? wp : diag_weight<R>(g, t, poly, ku, n, p, lattice_coord(kx, g));
+    const cplx<R> gs = cmulc(wt * a, rot);  // exp(-i psi) D^T A^H
+    grad_s[base + p] = gs;
+    if (want_phase) acc_phase += (double)gs.y * (double)sp.x - (double)gs.x * (double)sp.y;
+  }
+  if (ffr) {
+    __syncthreads();
+    const int r = g.band_r;
+    for (int p = threadIdx.x; p < g.n_freq; p += NT) {
+      cplx<R> a = {0, 0};
+      for (int o = -r; o <= r; ++o) {  // (D^T x)_p = sum_o D_{p+o, p} x_{p+o}
+        const int pp = p + o;
+        if (pp >= 0 && pp < g.n_freq) a = a + w[(base + pp) * (2 * r + 1) + (r - o)] * gbuf[pp];
+      }
+      const cplx<R> gs = cmulc(a, rot);
+      grad_s[base + p] = gs;
+      if (want_phase) {
+        const cplx<R> sv = load_sample<R>(samples, stype, base + p);
+        acc_phase += (double)gs.y * (double)sv.x - (double)gs.x * (double)sv.y;
+      }
+    }
+  }
+  if (want_phase) {
+    const double tot = block_sum<NT>(acc_phase);
+    if (threadIdx.x == 0) {
+      if (grad_phase) grad_phase[n] = (R)tot;
+      if (grad_dalong) grad_dalong[n] = (R)((double)t.ky[n] * tot);
+    }
+  }
+}
+
+// ============================================================================ launchers
+#ifdef TFFR_EMIT_SHARED
+int rows_threads(int logn) {
+  switch (logn) {
+    case 6: return nt_for<6>();
+    case 7: return nt_for<7>();
+    case 8: return nt_for<8>();
+    case 9: return nt_for<9>();
+    case 10: return nt_for<10>();
+    case 11: return nt_for<11>();
+    case 12: return nt_for<12>();
+    case 13: return nt_for<13>();
+    case 14: return nt_for<14>();
+  }
+  return 0;
+}
+#endif
+
+template <typename R>
+hipError_t launch_fwd_rows(const Geo& g, const Tab<R>& t, int stype, const void* samples, const R* phase,
+                           const R* dalong, const R* w, cplx<R>* out, int stage, hipStream_t st) {
+  const size_t lds = sizeof(cplx<R>) * (((size_t)1 << g.lognfx) + ((size_t)1 << g.lognfx) / 64 + 64) +
+                     sizeof(float) * kPolyLds;
+  if (g.range_mode == 1 && g.W > kRunWindow) return hipErrorInvalidValue;
+  TFFR_LOGN_DISPATCH(g.lognfx, {
+    constexpr int NT = nt_for<L>();
+    auto fn = g.range_mode == 1
+                  ? k_fwd_rows_run<R, L, NT, kRunWindow>
+                  : (g.sub <= 4 ? k_fwd_rows<R, L, NT, 4>
+                                : (g.sub <= 8 ? k_fwd_rows<R, L, NT, 8> : k_fwd_rows<R, L, NT, 16>));
+    hipError_t e = allow_lds((const void*)fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3(g.n_pulses), dim3(NT), lds, st, g, t, stype, samples, phase, dalong, w, out, stage);
+    return hipGetLastError();
+  })
+}
+
+template <typename R>
+hipError_t launch_adj_rows(const Geo& g, const Tab<R>& t, int stype, const cplx<R>* hx, const void* samples,
+                           const R* phase, const R* dalong, const R* w, cplx<R>* grad_s, R* grad_phase,
+                           R* grad_dalong, const EntComb<R>& ec, hipStream_t st) {
+  size_t lds = sizeof(cplx<R>) * (((size_t)1 << g.lognfx) + ((size_t)1 << g.lognfx) / 64 + 64) +
+               sizeof(float) * kPolyLds;
+  if (g.weighting == 2) lds += sizeof(cplx<R>) * (size_t)g.n_freq;
+  TFFR_LOGN_DISPATCH(g.lognfx, {
+    constexpr int NT = nt_for<L>();
+    // short slices on a 2048-point row: twice the threads shorten the per-sample gather
+    // (at most two samples per thread); longer slices keep the FFT's thread count
+    constexpr int NT2 = L == 11 ? 512 : NT;
+    const bool wide = NT2 != NT && g.n_freq <= 2 * NT2;
+    auto fn = wide ? k_adj_rows<R, L, NT2> : k_adj_rows<R, L, NT>;
+    hipError_t e = allow_lds((const void*)fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3(g.n_pulses), dim3(wide ? NT2 : NT), lds, st, g, t, stype, hx, samples, phase, dalong,
+                       w, grad_s, grad_phase, grad_dalong, ec);
+    return hipGetLastError();
+  })
+}
+
+#define TFFR_INSTANTIATE(R) \
+  template hipError_t launch_fwd_rows<R>(const Geo&, const Tab<R>&, int, const void*, const R*, const R*, const R*, cplx<R>*, int, hipStream_t); \
+  template hipError_t launch_adj_rows<R>(const Geo&, const Tab<R>&, int, const cplx<R>*, const void*, const R*, const R*, const R*, cplx<R>*, R*, R*, const EntComb<R>&, hipStream_t);
+
+TFFR_INSTANTIATE_TYPES
+
+}  // namespace tffr

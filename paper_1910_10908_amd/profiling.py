@@ -20,13 +20,18 @@ import sqlite3
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCE = os.path.join(HERE, "csrc", "tffr_kernels.hip")
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in
+                  ("tffr_device.h", "tffr_range.hip", "tffr_azimuth.hip", "tffr_entstep.hip",
+                                                  "tffr_coord.hip", "tffr_misc.hip")]
 COPY_BYTES = 64 << 20  # the calibration copy bench.py --profile-steps launches
 
 
 def kernel_source_hash():
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def _short(name):
