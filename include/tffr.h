@@ -69,7 +69,8 @@ enum {
 };
 
 /* What R_tau compares (Sec. III-B): the entries of the inverted diagonal as written
- * (keep iff 1/g >= tau), or the correlation g itself (keep iff g >= tau). */
+ * (keep iff |1/g| >= tau), or the correlation g itself (keep iff g >= tau).  The FP32
+ * and FP64 paths take the same decision (values within 1e-5 of tau are decided in FP64). */
 enum { TFFR_THRESH_LITERAL = 0, TFFR_THRESH_CORRELATION = 1 };
 
 enum { TFFR_C64 = 0, TFFR_C128 = 1, TFFR_C64_FP16IN = 2 };
@@ -91,7 +92,8 @@ typedef struct {
   int32_t weighting;    /* TFFR_W_*                                                   */
   double window_a;      /* w(x) = exp(-a |x - 1/2|), a = 0.01 in Sec. IV; >= 0        */
   double q;             /* truncation of W and Psi in lattice units, >= 1 (default 3) */
-  int32_t band_r;       /* plain-FFR band B_r, r = 2 in Sec. IV; 0..8                 */
+  int32_t band_r;       /* plain-FFR band B_r, r = 2 in Sec. IV; 0..8 (the solve covers
+                           max(r, half-band of the frame product) diagonals)           */
   double tau;           /* threshold, tau = 0.97 in Sec. IV; > 0                      */
   int32_t thresh_mode;  /* TFFR_THRESH_*                                              */
   int32_t kernel_width; /* gridding taps: 2..16 (7 gives ~1e-6 relative error)        */

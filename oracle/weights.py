@@ -59,15 +59,17 @@ def frame_diagonal(lam, a=0.01, q=3.0):
     return np.sum(np.where(mask, terms, 0.0), axis=-1)
 
 
-def tffr_weights(lam, a=0.01, q=3.0, tau=0.97, mode=THRESH_LITERAL):
-    """tFFR weights D = R_tau(pinv(diag(Psi W))) for every sample (Sec. III-B/III-C).
+def threshold_diagonal(g, tau=0.97, mode=THRESH_LITERAL):
+    """R_tau applied to the pseudo-inverse of a diagonal with entries g (Sec. III-B).
 
-    Returns (d, kept) with d the weight (0 where thresholded) and kept the boolean mask
-    of surviving samples; kept.sum() is the count c of Sec. III-C.
+    pinv(diag(g)) = diag(1/g) with 1/0 -> 0.  R_tau keeps an entry x iff x >= tau
+    (inclusive); on real entries of either sign it is read as |x| >= tau.  Mode 0 applies
+    it to the entries 1/g of the pseudo-inverse; mode 1 to the correlation g itself
+    (keep iff g >= tau, so a negative g is never kept).  Returns (d, kept).
     """
-    g = frame_diagonal(lam, a, q)
+    g = np.asarray(g, dtype=np.float64)
     with np.errstate(divide="ignore"):
-        inv = np.where(g != 0.0, 1.0 / g, 0.0)
+        inv = np.where(g != 0.0, 1.0 / np.where(g != 0.0, g, 1.0), 0.0)
     if mode == THRESH_LITERAL:
         kept = np.abs(inv) >= tau
     elif mode == THRESH_CORRELATION:
@@ -75,6 +77,15 @@ def tffr_weights(lam, a=0.01, q=3.0, tau=0.97, mode=THRESH_LITERAL):
     else:
         raise ValueError("unknown threshold mode")
     return np.where(kept, inv, 0.0), kept
+
+
+def tffr_weights(lam, a=0.01, q=3.0, tau=0.97, mode=THRESH_LITERAL):
+    """tFFR weights D = R_tau(pinv(diag(Psi W))) for every sample (Sec. III-B/III-C).
+
+    Returns (d, kept) with d the weight (0 where thresholded) and kept the boolean mask
+    of surviving samples; kept.sum() is the count c of Sec. III-C.
+    """
+    return threshold_diagonal(frame_diagonal(lam, a, q), tau, mode)
 
 
 def quad_weights(lam):
@@ -107,13 +118,10 @@ def frame_product_row(lam_row, a=0.01, q=3.0):
     G = np.zeros((n_p, n_p))
     for p in range(n_p):
         m, mask = grid_points(lam_row[p], q)
-        m = m[mask]
-        for pp in range(n_p):
-            ok = np.abs(m - lam_row[pp]) < q
-            if not np.any(ok):
-                continue
-            mm = m[ok]
-            G[p, pp] = np.sum(r_psi(mm - lam_row[p], a) * r_w(mm - lam_row[pp], a))
+        m = m[mask]  # the grid points Psi reaches from sample p
+        d_w = m[None, :] - lam_row[:, None]  # [p', m]: offsets of the same points from every sample
+        ok = np.abs(d_w) < q  # ... which W reaches from sample p'
+        G[p] = np.sum(np.where(ok, r_psi(m - lam_row[p], a)[None, :] * r_w(d_w, a), 0.0), axis=1)
     return G
 
 

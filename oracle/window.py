@@ -57,8 +57,3 @@ def r_psi(d, a):
     if a == 0.0:
         out = np.where(d == 0.0, 1.0, out)
     return out
-
-
-def window(x, a):
-    """w(x) = exp(-a |x - 1/2|) on the unit interval (Sec. IV, Baselines)."""
-    return np.exp(-float(a) * np.abs(np.asarray(x, dtype=np.float64) - 0.5))

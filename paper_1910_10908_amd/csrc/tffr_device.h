@@ -361,10 +361,15 @@ __device__ __forceinline__ R tffr_weight(const Geo& g, const float* poly, double
     float v = c[0];
 #pragma unroll
     for (int i = 1; i <= kPolyDeg; ++i) v = fmaf(v, t, c[i * kPolySeg]);
+    // the same predicates as the FP64 path: literal |1/g| >= tau; correlation g >= tau,
+    // i.e. 1/g > 0 and 1/g <= 1/tau (thr_f holds tau or 1/tau)
     const float thr = g.thr_f;
-    if (fabsf(v - thr) > g.near_f * thr) {
-      const bool keep = g.thresh_mode == 0 ? (v >= thr) : (v <= thr);
-      return keep ? (R)v : (R)0;
+    if (g.thresh_mode == 0) {
+      const float av = fabsf(v);
+      if (fabsf(av - thr) > g.near_f * thr) return av >= thr ? (R)v : (R)0;
+    } else {
+      if (!(v > 0.0f)) return (R)0;
+      if (fabsf(v - thr) > g.near_f * thr) return v <= thr ? (R)v : (R)0;
     }
   }
   return (R)tffr_weight_f64(delta, g.a, g.q, g.ema2, g.epa2, g.tau, g.thresh_mode);

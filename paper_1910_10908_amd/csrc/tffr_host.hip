@@ -695,7 +695,9 @@ tffr_status plan_create(const tffr_params* p, const double* k, const double* ku,
   off = align_up(off + sizeof(int));
   if (p->weighting == TFFR_W_FFR) {
     P->ffr_halfband = ffr_halfband(p, hkx);
-    g.band_b = P->ffr_halfband;
+    // the selected inversion yields the inverse on the band it factors; B_r may reach
+    // beyond the frame product's own half-band, so factor with the wider of the two
+    g.band_b = std::max(P->ffr_halfband, p->band_r);
     if ((size_t)p->n_freq * (2 * g.band_b + 1) * sizeof(double) > lds_max) return fail(TFFR_ERR_UNSUPPORTED);
     const size_t N = (size_t)p->n_pulses * p->n_freq;
     const size_t KT = 2 * ((size_t)std::ceil(p->q) + 1) + 1;

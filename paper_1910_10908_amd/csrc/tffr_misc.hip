@@ -362,6 +362,8 @@ hipError_t launch_ffr(const Geo& g, const Tab<R>& t, double* scratch, R* dband, 
     TFFR_FFR_SOLVE(4)
     TFFR_FFR_SOLVE(5)
     TFFR_FFR_SOLVE(6)
+    TFFR_FFR_SOLVE(7)
+    TFFR_FFR_SOLVE(8)
     default:
       return hipErrorInvalidValue;
   }

@@ -212,9 +212,55 @@ def test_k5_window_closed_forms_vs_quadrature():
     assert check_window_transforms(a=0.7) < 1e-13
 
 
-def test_k5_window_function():
-    x = np.linspace(0, 1, 11)
-    assert np.allclose(window.window(x, 0.01), np.exp(-0.01 * np.abs(x - 0.5)), rtol=0, atol=0)
+def check_frame_product_orientation(wts=weights, a=0.01, q=3.0):
+    """The frame product of Algorithm 1 built entry by entry from its definitions, by
+    quadrature on the un-centred unit interval, for one slice:
+
+        Psi[p, m] = <e^{2 pi i lam_p x}, e^{2 pi i l_m x} / w(x)>        (P x M)
+        W[m, p]   = w_hat(l_m - lam_p) = int_0^1 w(x) e^{-2 pi i (l_m - lam_p) x} dx   (M x P)
+
+    both truncated to |l_m - lam_p| < q, l_m the integers.  Then
+    (Psi W)[p, p'] = e^{i pi (lam_p + lam_p')} G~[p, p'] with G~ the oracle's real product
+    (R_Psi on the row sample, R_W on the column sample): the phases of the two
+    transforms combine to e^{i pi lam_p} e^{i pi lam_p'} because e^{-2 pi i l_m} = 1.
+    Returns the largest deviation; a transposed G~ misses by its asymmetry (~1e-4 here)."""
+    lam = np.array([50.2, 51.63, 53.41, 54.9, 56.07, 57.77])
+    m = np.arange(int(np.floor(lam.min() - q)), int(np.ceil(lam.max() + q)) + 1)
+    Psi = np.zeros((lam.size, m.size), complex)
+    Wm = np.zeros((m.size, lam.size), complex)
+    for p, lp in enumerate(lam):
+        for j, lm in enumerate(m):
+            if abs(lm - lp) < q:
+                Psi[p, j] = _quad_complex(lambda x: np.exp(2j * np.pi * lp * x) * np.conj(
+                    np.exp(2j * np.pi * lm * x) * np.exp(a * abs(x - 0.5))), 0, 1, [0.5])
+                Wm[j, p] = _quad_complex(lambda x: np.exp(-a * abs(x - 0.5)) * np.exp(-2j * np.pi * (lm - lp) * x),
+                                         0, 1, [0.5])
+    G = wts.frame_product_row(lam, a, q)
+    ph = np.exp(1j * np.pi * lam)
+    return float(np.max(np.abs(Psi @ Wm - ph[:, None] * G * ph[None, :])))
+
+
+def test_frame_product_orientation_from_definitions():
+    """Psi W from quadrature of the defining inner products equals the oracle's G~ up to
+    the phases of the un-centred interval; the product is far from symmetric at a = 0.01,
+    so this fixes which sample carries R_Psi and which R_W."""
+    assert check_frame_product_orientation() < 1e-12
+    lam = np.array([50.2, 51.63, 53.41, 54.9, 56.07, 57.77])
+    G = weights.frame_product_row(lam, 0.01, 3.0)
+    assert np.max(np.abs(G - G.T)) > 1e-5
+
+
+def test_threshold_reading_on_signed_values():
+    """R_tau on the pseudo-inverse of a diagonal, both readings, on values of either sign
+    (the weights the method produces are positive; this fixes the rule itself):
+    mode 0 keeps 1/g iff |1/g| >= tau (inclusive), mode 1 keeps iff g >= tau; 1/0 -> 0."""
+    g = np.array([1.0, 2.0, 2.5, -1.25, -4.0, 0.0, 1.5, 0.5])  # exact reciprocals around tau = 0.5
+    d0, k0 = weights.threshold_diagonal(g, 0.5, weights.THRESH_LITERAL)
+    assert list(k0) == [True, True, False, True, False, False, True, True]
+    assert d0[3] == -0.8 and d0[5] == 0.0 and d0[2] == 0.0 and d0[1] == 0.5
+    d1, k1 = weights.threshold_diagonal(g, 0.5, weights.THRESH_CORRELATION)
+    assert list(k1) == [True, True, True, False, False, False, True, True]
+    assert d1[2] == 0.4 and d1[3] == 0.0 and d1[7] == 2.0
 
 
 # ---------------------------------------------------------------- K6: limits
@@ -491,6 +537,9 @@ def test_mutations_are_caught():
     # adjoint missing its conjugation
     bad = _Patched(nudft, adjoint=lambda y, kx, ky, X, Y: np.conj(nudft.adjoint(np.conj(y), kx, ky, X, Y)))
     assert check_adjoint(bad) > 1e-3
+    # frame product transposed (R_W on the row sample, R_Psi on the column sample)
+    bad_w = _Patched(weights, frame_product_row=lambda lam, a=0.01, q=3.0: weights.frame_product_row(lam, a, q).T)
+    assert check_frame_product_orientation(bad_w) > 1e-6
 
 
 def test_oracle_package_docstring_marks_test_infrastructure():
