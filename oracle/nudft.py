@@ -15,7 +15,24 @@ with no global normalisation (the 1/N of Eq. (1) is absorbed).  Images are store
 range-major: index [jx, jy].
 """
 
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
+
+
+def _row_chunks(n_rows, workers):
+    step = max(1, -(-n_rows // max(1, workers)))
+    return [(a, min(a + step, n_rows)) for a in range(0, n_rows, step)]
+
+
+def _map_rows(fn, n_rows, workers):
+    """fn(a, b) on consecutive row ranges, on `workers` threads (NumPy's exponentials and
+    products release the GIL); the results in row order."""
+    chunks = _row_chunks(n_rows, workers)
+    if len(chunks) <= 1:
+        return [fn(a, b) for a, b in chunks]
+    with ThreadPoolExecutor(len(chunks)) as ex:
+        return list(ex.map(lambda ab: fn(*ab), chunks))
 
 
 def forward_direct(c, kx, ky, X, Y):
@@ -29,23 +46,29 @@ def forward_direct(c, kx, ky, X, Y):
     return out
 
 
-def forward_separable(c, kx, ky, X, Y):
+def forward_separable(c, kx, ky, X, Y, workers=1):
     """Same sum, factored through the slice structure (ky constant along a row).
 
     T[n, jx] = sum_p c[n,p] exp(i kx[n,p] X[jx]);  I[jx, jy] = sum_n T[n, jx] exp(i ky[n] Y[jy]).
+    With workers > 1 the rows are split into that many ranges whose partial images are
+    formed on threads and added.
     """
     c = np.asarray(c, dtype=np.complex128)
-    T = np.empty((c.shape[0], X.size), dtype=np.complex128)
-    for n in range(c.shape[0]):
-        T[n] = np.exp(1j * np.outer(X, kx[n])) @ c[n]
-    Ey = np.exp(1j * np.outer(ky, Y))  # [n, jy]
-    return T.T @ Ey
+
+    def rows(a, b):
+        T = np.empty((b - a, X.size), dtype=np.complex128)
+        for n in range(a, b):
+            T[n - a] = np.exp(1j * np.outer(X, kx[n])) @ c[n]
+        Ey = np.exp(1j * np.outer(ky[a:b], Y))  # [n, jy]
+        return T.T @ Ey
+
+    return sum(_map_rows(rows, c.shape[0], workers))
 
 
-def forward_columns(c, kx, ky, X, Y, cols):
+def forward_columns(c, kx, ky, X, Y, cols, workers=1):
     """The separable sum restricted to the range columns `cols` -> [len(cols), len(Y)]."""
     Xs = np.asarray(X)[np.asarray(cols)]
-    return forward_separable(c, kx, ky, Xs, Y)
+    return forward_separable(c, kx, ky, Xs, Y, workers)
 
 
 def forward_pixels(c, kx, ky, X, Y, pix):
@@ -57,15 +80,20 @@ def forward_pixels(c, kx, ky, X, Y, pix):
     return out
 
 
-def adjoint(y, kx, ky, X, Y):
-    """Adjoint of the forward sum: out[n,p] = sum_{jx,jy} y[jx,jy] exp(-i(kx X + ky Y))."""
+def adjoint(y, kx, ky, X, Y, workers=1):
+    """Adjoint of the forward sum: out[n,p] = sum_{jx,jy} y[jx,jy] exp(-i(kx X + ky Y)).
+    Rows are independent; workers > 1 forms row ranges on threads."""
     y = np.asarray(y, dtype=np.complex128)
-    Ey = np.exp(-1j * np.outer(ky, Y))  # [n, jy]
-    Z = Ey @ y.T  # [n, jx]
-    out = np.empty(kx.shape, dtype=np.complex128)
-    for n in range(kx.shape[0]):
-        out[n] = np.exp(-1j * np.outer(kx[n], X)) @ Z[n]
-    return out
+
+    def rows(a, b):
+        Ey = np.exp(-1j * np.outer(ky[a:b], Y))  # [n, jy]
+        Z = Ey @ y.T  # [n, jx]
+        out = np.empty((b - a,) + kx.shape[1:], dtype=np.complex128)
+        for n in range(a, b):
+            out[n - a] = np.exp(-1j * np.outer(kx[n], X)) @ Z[n - a]
+        return out
+
+    return np.concatenate(_map_rows(rows, kx.shape[0], workers), axis=0)
 
 
 def adjoint_samples(y, kx, ky, X, Y, samples):

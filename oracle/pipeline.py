@@ -109,22 +109,22 @@ def weighted_samples(prob, s, phase=None, dalong=None, user_w=None):
     return apply_weights(sample_weights(prob, user_w), sp)
 
 
-def image(prob, s, phase=None, dalong=None, user_w=None, form="separable"):
+def image(prob, s, phase=None, dalong=None, user_w=None, form="separable", workers=1):
     """The reconstructed image I[jx, jy] (range-major)."""
     kx, ky, lam, X, Y = prob.geometry()
     c = weighted_samples(prob, s, phase, dalong, user_w)
     if form == "direct":
         return nudft.forward_direct(c, kx, ky, X, Y)
-    return nudft.forward_separable(c, kx, ky, X, Y)
+    return nudft.forward_separable(c, kx, ky, X, Y, workers)
 
 
-def image_columns(prob, s, cols, phase=None, dalong=None, user_w=None):
+def image_columns(prob, s, cols, phase=None, dalong=None, user_w=None, workers=1):
     kx, ky, lam, X, Y = prob.geometry()
     c = weighted_samples(prob, s, phase, dalong, user_w)
-    return nudft.forward_columns(c, kx, ky, X, Y, cols)
+    return nudft.forward_columns(c, kx, ky, X, Y, cols, workers)
 
 
-def backward(prob, grad_image, s, phase=None, dalong=None, user_w=None):
+def backward(prob, grad_image, s, phase=None, dalong=None, user_w=None, workers=1):
     """Gradients of a real loss given grad_image = dL/dRe I + i dL/dIm I.
 
     Returns (grad_s, grad_phase, grad_dalong).
@@ -133,7 +133,7 @@ def backward(prob, grad_image, s, phase=None, dalong=None, user_w=None):
     psi = row_phase(ky, phase, dalong)
     rot = np.exp(1j * psi)[:, None]
     sp = np.asarray(s, dtype=np.complex128) * rot
-    grad_c = nudft.adjoint(grad_image, kx, ky, X, Y)
+    grad_c = nudft.adjoint(grad_image, kx, ky, X, Y, workers)
     grad_sp = apply_weights(sample_weights(prob, user_w), grad_c, transpose=True)
     grad_s = grad_sp * np.conj(rot)
     dpsi = np.sum(np.real(np.conj(grad_sp) * 1j * sp), axis=1)

@@ -119,36 +119,70 @@ def frame_product_row(lam_row, a=0.01, q=3.0):
     for p in range(n_p):
         m, mask = grid_points(lam_row[p], q)
         m = m[mask]  # the grid points Psi reaches from sample p
-        d_w = m[None, :] - lam_row[:, None]  # [p', m]: offsets of the same points from every sample
+        # a point within q of both samples needs |lam_p - lam_p'| < 2q: only those columns
+        near = np.nonzero(np.abs(lam_row - lam_row[p]) < 2.0 * q)[0]
+        d_w = m[None, :] - lam_row[near][:, None]  # [p', m]: offsets of the same points
         ok = np.abs(d_w) < q  # ... which W reaches from sample p'
-        G[p] = np.sum(np.where(ok, r_psi(m - lam_row[p], a)[None, :] * r_w(d_w, a), 0.0), axis=1)
+        G[p, near] = np.sum(np.where(ok, r_psi(m - lam_row[p], a)[None, :] * r_w(d_w, a), 0.0), axis=1)
     return G
+
+
+def pinv(G):
+    """Moore-Penrose pseudo-inverse of a square real matrix.
+
+    A nonsingular G's pseudo-inverse is its inverse, computed here from the LU
+    factorisation when LAPACK's reciprocal condition estimate exceeds 1e-12 (the frame
+    products of slices whose samples are more than a lattice unit apart have condition
+    numbers of 2-3); otherwise the SVD-based numpy.linalg.pinv with its default cut-off.
+    """
+    from scipy.linalg import lapack
+
+    G = np.asarray(G, dtype=np.float64)
+    lu, piv, info = lapack.dgetrf(G)
+    if info == 0:
+        rcond, info_c = lapack.dgecon(lu, np.linalg.norm(G, 1), norm="O")
+        if info_c == 0 and rcond > 1e-12:
+            Z, info_i = lapack.dgetri(lu, piv)
+            if info_i == 0:
+                return Z
+    return np.linalg.pinv(G)
 
 
 def ffr_weights_row(lam_row, a=0.01, q=3.0, r=2):
     """Plain FFR weights for one slice: D = B_r(pinv(G~)) (Eq. (8))."""
     G = frame_product_row(lam_row, a, q)
-    Z = np.linalg.pinv(G)
+    Z = pinv(G)
     n_p = lam_row.size
     idx = np.arange(n_p)
     band = np.abs(idx[:, None] - idx[None, :]) <= r
     return np.where(band, Z, 0.0)
 
 
-def ffr_weights(lam, a=0.01, q=3.0, r=2):
+def ffr_weights(lam, a=0.01, q=3.0, r=2, workers=1):
     """Plain FFR banded weights for every slice, stored as [n_pulses][n_freq][2r+1].
 
     Entry [n, p, r + o] is D^{(n)}_{p, p+o} for o in [-r, r] (0 outside the row).
+    Slices are independent; workers > 1 solves them on threads.
     """
     lam = np.atleast_2d(np.asarray(lam, dtype=np.float64))
     n_rows, n_p = lam.shape
     out = np.zeros((n_rows, n_p, 2 * r + 1))
-    for n in range(n_rows):
+
+    def one(n):
         D = ffr_weights_row(lam[n], a, q, r)
         for o in range(-r, r + 1):
             for p in range(n_p):
                 if 0 <= p + o < n_p:
                     out[n, p, r + o] = D[p, p + o]
+
+    if workers > 1:
+        from concurrent.futures import ThreadPoolExecutor
+
+        with ThreadPoolExecutor(workers) as ex:
+            list(ex.map(one, range(n_rows)))
+    else:
+        for n in range(n_rows):
+            one(n)
     return out
 
 

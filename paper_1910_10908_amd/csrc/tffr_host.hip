@@ -562,6 +562,8 @@ tffr_status plan_create(const tffr_params* p, const double* k, const double* ku,
   // staged-spectra space, at least [CB][nfy] more
   P->ent_fused = ((size_t)nfy * cb + std::max<size_t>((size_t)p->n_pulses * cb, (size_t)nfy * cb) + twy_n) * csz <=
                  lds_max;
+  if (const char* e = std::getenv("TFFR_ENT_FUSED"))  // 0: force the image round trip
+    if (std::atoi(e) == 0) P->ent_fused = false;
   // coordinate gradients: two fields per fine row / column in LDS
   if ((2 * (size_t)nfx + twx_n) * csz + 2048 <= lds_max)
     for (int c = cb; c >= 1 && !P->coord_cb; c >>= 1)
