@@ -56,8 +56,13 @@ typedef enum {
   TFFR_ERR_UNSUPPORTED = 5,  /* width, dtype, grid size or FFR band not supported   */
   TFFR_ERR_SINGULAR = 6,     /* plain-FFR frame product has a vanishing pivot       */
   TFFR_ERR_NOMEM = 7,        /* device or host allocation of plan tables failed     */
-  TFFR_ERR_HIP = 8           /* a HIP runtime call failed                           */
+  TFFR_ERR_HIP = 8,          /* a HIP runtime call failed                           */
+  TFFR_ERR_SCRATCH = 9       /* tffr_entropy_step_noalloc: the plan's step needs more
+                                than TFFR_SCRATCH_BYTES                               */
 } tffr_status;
+
+/* Size of the static device array tffr_entropy_step_noalloc works in (per GPU). */
+#define TFFR_SCRATCH_BYTES (32u << 20)
 
 /* Weighting methods: the alpha_n / D of Eqs. (1), (4) and (8). */
 enum {
@@ -203,6 +208,24 @@ tffr_status tffr_entropy_step(tffr_plan *plan, const void *d_samples, const void
                               const void *d_dalong, const void *d_user_w, void *d_image,
                               double *d_loss, void *d_grad_samples, void *d_grad_phase,
                               void *d_grad_dalong, void *d_work, tffr_stream stream);
+
+/* tffr_entropy_step without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): it works in a static device array of TFFR_SCRATCH_BYTES (32 MiB) that the
+ * library holds on each GPU it runs on until the process ends, and calls no allocating
+ * routine.  Arguments and results as tffr_entropy_step, all caller-owned.
+ *  - TFFR_ERR_SCRATCH when the plan's step needs more than TFFR_SCRATCH_BYTES (its range
+ *    spectra and two gradient fields take 24 n_pulses mx bytes in complex64: up to
+ *    512 x 1024 -> 1024^2 and 1024 x 2048 -> 1024^2 fit, 2048 x 4096 -> 2048^2 does not);
+ *    TFFR_ERR_HIP when the array's device address could not be resolved at plan creation.
+ *  - Every call on one GPU shares that GPU's array and leaves its contents behind; the
+ *    step writes every scratch value before reading it, so nothing needs clearing, but
+ *    calls that overlap on one GPU (concurrent streams, threads) race and corrupt each
+ *    other.  Serialise them. */
+tffr_status tffr_entropy_step_noalloc(tffr_plan *plan, const void *d_samples, const void *d_phase,
+                                      const void *d_dalong, const void *d_user_w, void *d_image,
+                                      double *d_loss, void *d_grad_samples, void *d_grad_phase,
+                                      void *d_grad_dalong, tffr_stream stream);
 
 /* Gradients with respect to the sample coordinates, for refining the geometry itself
  * (the method's weights held fixed as constants of the geometry):

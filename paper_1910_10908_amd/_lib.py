@@ -12,7 +12,9 @@ LIB_PATH = os.path.join(HERE, "libtffr.so")
 TFFR_OK = 0
 STATUS_NAMES = {0: "TFFR_OK", 1: "TFFR_ERR_ARG", 2: "TFFR_ERR_EVANESCENT", 3: "TFFR_ERR_NONMONOTONE",
                 4: "TFFR_ERR_LAYOUT", 5: "TFFR_ERR_UNSUPPORTED", 6: "TFFR_ERR_SINGULAR", 7: "TFFR_ERR_NOMEM",
-                8: "TFFR_ERR_HIP"}
+                8: "TFFR_ERR_HIP", 9: "TFFR_ERR_SCRATCH"}
+TFFR_ERR_SCRATCH = 9
+SCRATCH_BYTES = 32 << 20
 
 W_NONE, W_QUAD, W_FFR, W_TFFR, W_USER = 0, 1, 2, 3, 4
 THRESH_LITERAL, THRESH_CORRELATION = 0, 1
@@ -59,6 +61,7 @@ _PROTOS = {
     "tffr_adjoint": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tffr_entropy": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "tffr_entropy_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "tffr_entropy_step_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tffr_row_phase_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "tffr_coord_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tffr_status_string": (ctypes.c_char_p, [ctypes.c_int]),

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -120,6 +121,32 @@ int log2_pow2_at_least(double v) {
   return l;
 }
 
+// ---------------------------------------------------------------- static scratch
+// Device memory of tffr_entropy_step_noalloc: one array per GPU in the code object, so a
+// call needs no allocation.  The array's host-side name is not a device address; the
+// address is taken once per device (with that device current) by hipGetSymbolAddress
+// and kept in scratch_addr[].
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[TFFR_SCRATCH_BYTES];
+std::mutex scratch_mutex;
+void* scratch_addr[kMaxDevices] = {};
+hipError_t scratch_err[kMaxDevices] = {};
+bool scratch_done[kMaxDevices] = {};
+
+// Address of this device's scratch array (set up on the first call per device; the
+// current device must be `dev`).  nullptr if the runtime could not resolve it.
+void* scratch_for_device(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (!scratch_done[dev]) {
+    void* ptr = nullptr;
+    scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    scratch_addr[dev] = scratch_err[dev] == hipSuccess ? ptr : nullptr;
+    scratch_done[dev] = true;
+  }
+  return scratch_addr[dev];
+}
+
 // ---------------------------------------------------------------- plan
 struct DevBuf {
   void* p = nullptr;
@@ -142,6 +169,8 @@ struct tffr_plan {
   // workspace layout
   bool ent_fused = false;  // entropy step uses the fused azimuth kernel
   int coord_cb = 0;        // azimuth block width of the coordinate-gradient kernels (0: unsupported)
+  void* scratch = nullptr;  // this device's static scratch array (tffr_entropy_step_noalloc)
+  size_t step_bytes = 0;    // workspace bytes tffr_entropy_step reads and writes
   size_t off_hx = 0, off_h12 = 0, off_cblk = 0, off_part = 0, off_stats = 0, off_kept = 0, off_count = 0, off_status = 0, off_gband = 0, off_zband = 0,
          off_dband = 0, work_bytes = 0;
   bool dbl() const { return prm.dtype == TFFR_C128; }
@@ -469,6 +498,7 @@ const char* tffr_status_string(tffr_status s) {
     case TFFR_ERR_SINGULAR: return "TFFR_ERR_SINGULAR: plain-FFR frame product is singular";
     case TFFR_ERR_NOMEM: return "TFFR_ERR_NOMEM: allocation failed";
     case TFFR_ERR_HIP: return "TFFR_ERR_HIP: HIP runtime error";
+    case TFFR_ERR_SCRATCH: return "TFFR_ERR_SCRATCH: the problem needs more than the static scratch array holds";
   }
   return "TFFR_ERR_UNKNOWN";
 }
@@ -689,6 +719,7 @@ tffr_status plan_create(const tffr_params* p, const double* k, const double* ku,
   off = align_up(off + sizeof(double) * 2 * std::max<size_t>(kEntropyParts, (p->mx + P->cb - 1) / P->cb));
   P->off_stats = off;
   off = align_up(off + sizeof(double) * 2);
+  P->step_bytes = off;  // the entropy step uses the regions above, nothing below
   P->off_kept = off;
   off = align_up(off + sizeof(unsigned long long) * kPartials);
   P->off_count = off;
@@ -731,6 +762,7 @@ tffr_status plan_create(const tffr_params* p, const double* k, const double* ku,
     if (st != 0) return fail(TFFR_ERR_SINGULAR);
   }
   if (hipDeviceSynchronize() != hipSuccess) return fail(TFFR_ERR_HIP);
+  P->scratch = scratch_for_device(P->device);  // device current: the plan's
   *out = P;
   return TFFR_OK;
 }
@@ -813,6 +845,18 @@ tffr_status tffr_entropy_step(tffr_plan* P, const void* smp, const void* ph, con
   hipStream_t st = (hipStream_t)stream;
   return P->dbl() ? do_entropy_step<double>(P, smp, ph, da, uw, img, loss, gs, gph, gda, work, st)
                   : do_entropy_step<float>(P, smp, ph, da, uw, img, loss, gs, gph, gda, work, st);
+}
+
+tffr_status tffr_entropy_step_noalloc(tffr_plan* P, const void* smp, const void* ph, const void* da, const void* uw,
+                                      void* img, double* loss, void* gs, void* gph, void* gda, tffr_stream stream) {
+  if (!P || !smp || !img || !loss || !gs) return TFFR_ERR_ARG;
+  if (P->prm.weighting == TFFR_W_USER && !uw) return TFFR_ERR_ARG;
+  if (P->step_bytes > (size_t)TFFR_SCRATCH_BYTES) return TFFR_ERR_SCRATCH;
+  if (!P->scratch) return TFFR_ERR_HIP;
+  if (!aligned(img, P->csize() / 2) || !aligned(gs, P->csize() / 2)) return TFFR_ERR_LAYOUT;
+  hipStream_t st = (hipStream_t)stream;
+  return P->dbl() ? do_entropy_step<double>(P, smp, ph, da, uw, img, loss, gs, gph, gda, P->scratch, st)
+                  : do_entropy_step<float>(P, smp, ph, da, uw, img, loss, gs, gph, gda, P->scratch, st);
 }
 
 tffr_status tffr_coord_grad(tffr_plan* P, const void* cot, const void* smp, const void* ph, const void* da,

@@ -217,6 +217,25 @@ class Plan:
                                               _ptr(self.work), _stream()), "tffr_entropy_step")
         return img, loss, gs, gph, gda
 
+    def tffr_entropy_step_noalloc(self, samples, phase=None, dalong=None, user_w=None, out=None):
+        """tffr_entropy_step_noalloc: the fused step in the library's static scratch array
+        (no workspace).  `out` = (image, loss, grad_samples, grad_phase, grad_dalong), each
+        may be None to allocate it here; returns the five."""
+        self._chk_samples(samples)
+        self._chk(phase, (self.params.n_pulses,), self.rtype, "phase")
+        self._chk(dalong, (self.params.n_pulses,), self.rtype, "dalong")
+        self._chk_weights(user_w)
+        img, loss, gs, gph, gda = out if out is not None else (None,) * 5
+        img = torch.empty(self.shape_image, dtype=self.ctype, device=self.device) if img is None else img
+        loss = torch.empty((), dtype=torch.float64, device=self.device) if loss is None else loss
+        gs = torch.empty(self.shape_samples, dtype=self.ctype, device=self.device) if gs is None else gs
+        gph = torch.empty(self.params.n_pulses, dtype=self.rtype, device=self.device) if gph is None else gph
+        gda = torch.empty(self.params.n_pulses, dtype=self.rtype, device=self.device) if gda is None else gda
+        _lib.check(self.lib.tffr_entropy_step_noalloc(self.handle, _ptr(samples), _ptr(phase), _ptr(dalong),
+                                                      _ptr(user_w), _ptr(img), _ptr(loss), _ptr(gs), _ptr(gph),
+                                                      _ptr(gda), _stream()), "tffr_entropy_step_noalloc")
+        return img, loss, gs, gph, gda
+
     def tffr_weights(self, out=None):
         shape = self.shape_samples
         if self.params.weighting == W_FFR:
