@@ -62,6 +62,20 @@ tffr_status tffr_debug_ent_adj_rows(tffr_plan *plan, const void *d_samples, cons
                                     void *d_grad_samples, void *d_grad_phase, void *d_grad_dalong,
                                     void *d_work, tffr_stream stream);
 
+/* Per-launch times of the entropy step: runs tffr_entropy_step `nsteps` times (arguments
+ * as there) with a HIP event recorded on `stream` before each of its launches and after
+ * the last, synchronising after every step, and returns the average time between
+ * consecutive events, i.e. of each launch in the step's own order and data flow:
+ *   ms_out  host float[7], receives *nkern averages (ms)
+ *   nkern   receives the number of launches (3 to 5)
+ *   names   host const char*[7] or NULL, receives the kernels' names (static strings)
+ * The events are created and destroyed inside the call. */
+tffr_status tffr_debug_step_kernel_times(tffr_plan *plan, const void *d_samples, const void *d_phase,
+                                         const void *d_dalong, const void *d_user_w, void *d_image, double *d_loss,
+                                         void *d_grad_samples, void *d_grad_phase, void *d_grad_dalong, void *d_work,
+                                         tffr_stream stream, int32_t nsteps, float *ms_out, int32_t *nkern,
+                                         const char **names);
+
 #ifdef __cplusplus
 }
 #endif

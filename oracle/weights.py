@@ -112,50 +112,75 @@ def frame_product_row(lam_row, a=0.01, q=3.0):
 
     G~_{pp'} = sum over integers m with |m - lam_p| < q and |m - lam_p'| < q of
     R_Psi(m - lam_p) R_W(m - lam_p')  (Psi truncated around lam_p, W around lam_p').
+    The samples of a slice are sorted by lam (kx rises along the slice); a grid point
+    within q of both samples needs |lam_p - lam_p'| < 2q, so each row sample p only meets
+    the column samples in that window, found by binary search.
     """
-    lam_row = np.asarray(lam_row, dtype=np.float64)
-    n_p = lam_row.size
+    lam = np.asarray(lam_row, dtype=np.float64)
+    n_p = lam.size
+    if n_p > 1 and not np.all(np.diff(lam) > 0):
+        raise ValueError("frame_product_row: lam must increase along the slice")
+    m, mask = grid_points(lam, q)  # [p, j]: the grid points Psi reaches from sample p
+    lo = np.searchsorted(lam, lam - 2.0 * q, side="right")  # first p' with lam_p' > lam_p - 2q
+    hi = np.searchsorted(lam, lam + 2.0 * q, side="left")  # one past the last p' < lam_p + 2q
+    width = int(np.max(hi - lo))
+    idx = lo[:, None] + np.arange(width)[None, :]  # [p, o]: candidate column samples
+    valid = idx < hi[:, None]
+    idx = np.minimum(idx, n_p - 1)
+    d_w = m[:, None, :] - lam[idx][:, :, None]  # [p, o, j]: offsets of p's points from p'
+    ok = mask[:, None, :] & valid[:, :, None] & (np.abs(d_w) < q)  # ... which W reaches from p'
+    terms = np.where(ok, r_psi(m - lam[:, None], a)[:, None, :] * r_w(d_w, a), 0.0)
     G = np.zeros((n_p, n_p))
-    for p in range(n_p):
-        m, mask = grid_points(lam_row[p], q)
-        m = m[mask]  # the grid points Psi reaches from sample p
-        # a point within q of both samples needs |lam_p - lam_p'| < 2q: only those columns
-        near = np.nonzero(np.abs(lam_row - lam_row[p]) < 2.0 * q)[0]
-        d_w = m[None, :] - lam_row[near][:, None]  # [p', m]: offsets of the same points
-        ok = np.abs(d_w) < q  # ... which W reaches from sample p'
-        G[p, near] = np.sum(np.where(ok, r_psi(m - lam_row[p], a)[None, :] * r_w(d_w, a), 0.0), axis=1)
+    rows = np.broadcast_to(np.arange(n_p)[:, None], idx.shape)
+    G[rows[valid], idx[valid]] = np.sum(terms, axis=2)[valid]
     return G
 
 
-def pinv(G):
+def pinv(G, band=None):
     """Moore-Penrose pseudo-inverse of a square real matrix.
 
-    A nonsingular G's pseudo-inverse is its inverse, computed here from the LU
-    factorisation when LAPACK's reciprocal condition estimate exceeds 1e-12 (the frame
-    products of slices whose samples are more than a lattice unit apart have condition
-    numbers of 2-3); otherwise the SVD-based numpy.linalg.pinv with its default cut-off.
+    A nonsingular G's pseudo-inverse is its inverse.  It is formed from an LU
+    factorisation with partial pivoting (LAPACK's banded one when G vanishes beyond `band`
+    diagonals, the frame products being banded) and used when the 1-norm condition number
+    ||G|| ||G^-1|| stays below 1e12 (the products of slices whose samples are more than a
+    lattice unit apart have 2-3); otherwise the SVD-based numpy.linalg.pinv with its
+    default cut-off.
     """
     from scipy.linalg import lapack
 
     G = np.asarray(G, dtype=np.float64)
-    lu, piv, info = lapack.dgetrf(G)
-    if info == 0:
-        rcond, info_c = lapack.dgecon(lu, np.linalg.norm(G, 1), norm="O")
-        if info_c == 0 and rcond > 1e-12:
-            Z, info_i = lapack.dgetri(lu, piv)
-            if info_i == 0:
-                return Z
+    n = G.shape[0]
+    Z = None
+    if band is not None and 0 <= band < n - 1:
+        kl = ku = int(band)
+        ab = np.zeros((2 * kl + ku + 1, n))
+        for d in range(-kl, ku + 1):  # LAPACK band storage: ab[kl + ku + i - j, j] = G[i, j]
+            j = np.arange(max(0, d), min(n, n + d))
+            ab[kl + ku - d, j] = G[j - d, j]
+        lu, ipiv, info = lapack.dgbtrf(ab, kl, ku)
+        if info == 0:
+            Z, info = lapack.dgbtrs(lu, kl, ku, np.eye(n), ipiv)
+            Z = Z if info == 0 else None
+    else:
+        lu, ipiv, info = lapack.dgetrf(G)
+        if info == 0:
+            Z, info = lapack.dgetri(lu, ipiv)
+            Z = Z if info == 0 else None
+    if Z is not None and np.all(np.isfinite(Z)) and np.linalg.norm(G, 1) * np.linalg.norm(Z, 1) < 1e12:
+        return Z
     return np.linalg.pinv(G)
 
 
 def ffr_weights_row(lam_row, a=0.01, q=3.0, r=2):
     """Plain FFR weights for one slice: D = B_r(pinv(G~)) (Eq. (8))."""
     G = frame_product_row(lam_row, a, q)
-    Z = pinv(G)
-    n_p = lam_row.size
+    nz = np.nonzero(G)
+    band = int(np.max(np.abs(nz[0] - nz[1]))) if nz[0].size else 0
+    Z = pinv(G, band)
+    n_p = np.asarray(lam_row).size
     idx = np.arange(n_p)
-    band = np.abs(idx[:, None] - idx[None, :]) <= r
-    return np.where(band, Z, 0.0)
+    keep = np.abs(idx[:, None] - idx[None, :]) <= r
+    return np.where(keep, Z, 0.0)
 
 
 def ffr_weights(lam, a=0.01, q=3.0, r=2, workers=1):
@@ -170,15 +195,19 @@ def ffr_weights(lam, a=0.01, q=3.0, r=2, workers=1):
 
     def one(n):
         D = ffr_weights_row(lam[n], a, q, r)
-        for o in range(-r, r + 1):
-            for p in range(n_p):
-                if 0 <= p + o < n_p:
-                    out[n, p, r + o] = D[p, p + o]
+        for o in range(-r, r + 1):  # diagonal o: D[p, p + o]
+            if o >= 0:
+                out[n, : max(n_p - o, 0), r + o] = np.diagonal(D, o)
+            else:
+                out[n, -o:, r + o] = np.diagonal(D, o)
 
     if workers > 1:
         from concurrent.futures import ThreadPoolExecutor
 
-        with ThreadPoolExecutor(workers) as ex:
+        from threadpoolctl import threadpool_limits
+
+        # one BLAS thread per worker: the slices are the parallelism
+        with threadpool_limits(limits=1), ThreadPoolExecutor(workers) as ex:
             list(ex.map(one, range(n_rows)))
     else:
         for n in range(n_rows):

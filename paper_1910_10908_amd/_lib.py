@@ -71,6 +71,9 @@ _PROTOS = {
     "tffr_debug_cols": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "tffr_debug_ent_cols": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "tffr_debug_ent_adj_rows": (ctypes.c_int, [_vp] * 11),
+    "tffr_debug_step_kernel_times": (ctypes.c_int, [_vp] * 12 + [ctypes.c_int32, ctypes.POINTER(ctypes.c_float),
+                                                                ctypes.POINTER(ctypes.c_int32),
+                                                                ctypes.POINTER(ctypes.c_char_p)]),
     "tffr_debug_plan_config": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                               ctypes.POINTER(ctypes.c_int32)]),
 }

@@ -82,7 +82,9 @@ __global__ __launch_bounds__(NT) void k_coord_rows(Geo g, Tab<R> t, int stype, c
   for (int p = threadIdx.x; p < g.n_freq; p += NT) {
     const double kx = kx_of(t, raw_k(t, g.n_freq, n, p), ku);
     const cplx<R> sp = ffr ? cplx<R>{0, 0} : load_sample<R>(samples, stype, base + p);
-    const cplx<R> c = weighted_sample<R>(g, t, poly, stype, samples, w, n, p, ku, lattice_coord(kx, g), rot, sp);
+    bool kept;
+    const cplx<R> c =
+        weighted_sample<R>(g, t, poly, stype, samples, w, n, p, ku, lattice_coord(kx, g), rot, sp, kept);
     cplx<R> ax = {0, 0}, ay = {0, 0};
     if (g.literal) {
       ax = lit_gather<R>(buf, N, kx * g.tx_scale, g.q, g.lit_taps, g.a, g.ema2);

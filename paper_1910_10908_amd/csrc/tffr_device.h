@@ -520,14 +520,18 @@ __device__ __attribute__((noinline)) cplx<R> ffr_apply(const void* samples, int 
 }
 
 // Weighted, phased sample c[n,p] (forward input of the gridding); s is sample (n, p).
+// `kept` is false when a diagonal weight is zero (a sample the threshold removes, Sec.
+// III-C): the caller then skips its taps.
 template <typename R>
 __device__ __forceinline__ cplx<R> weighted_sample(const Geo& g, const Tab<R>& t, const float* poly, int stype,
                                                    const void* samples, const R* w, int n, int p,
-                                                   double ku, double lam, cplx<R> rot, cplx<R> s) {
+                                                   double ku, double lam, cplx<R> rot, cplx<R> s, bool& kept) {
   const size_t base = (size_t)n * g.n_freq;
+  kept = true;
   if (g.weighting == 2)  // plain FFR: banded D within the slice
     return cmul(rot, ffr_apply<R>(samples, stype, w, base, p, g.n_freq, g.band_r));
   const R wt = w ? w[base + p] : diag_weight<R>(g, t, poly, ku, n, p, lam);
+  kept = wt != (R)0;
   return wt * cmul(rot, s);
 }
 

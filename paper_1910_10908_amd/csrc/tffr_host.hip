@@ -376,9 +376,12 @@ hipError_t launch_ent_adj_rows(tffr_plan* P, const void* smp, const void* ph, co
                                   (const R*)ph, (const R*)da, w, (cplx<R>*)gs, (R*)gph, (R*)gda, ec, st);
 }
 
+// The step's launches in order; with `mark` non-null, mark(i) runs before launch i and
+// mark(nk) after the last (per-launch timing), and *nk receives the number of launches.
 template <typename R>
 tffr_status do_entropy_step(tffr_plan* P, const void* smp, const void* ph, const void* da, const void* uw, void* img,
-                            double* loss, void* gs, void* gph, void* gda, void* work, hipStream_t st) {
+                            double* loss, void* gs, void* gph, void* gda, void* work, hipStream_t st,
+                            hipError_t (*mark)(void*, int) = nullptr, void* mark_ctx = nullptr, int* nk = nullptr) {
   const tffr::Tab<R> t = tables<R>(P);
   const R* w = (const R*)uw;
   if (!w && P->prm.weighting == TFFR_W_FFR) w = (const R*)P->ffr_d.p;
@@ -389,27 +392,64 @@ tffr_status do_entropy_step(tffr_plan* P, const void* smp, const void* ph, const
   const int nparts = (P->prm.mx + P->cb - 1) / P->cb;
   cplx<R>* h12 = (cplx<R>*)(wb + P->off_h12);
   R* cblk = (R*)(wb + P->off_cblk);
+  int k = 0;
+  auto step = [&](hipError_t e) -> hipError_t {
+    if (e == hipSuccess && mark) e = mark(mark_ctx, k);
+    ++k;
+    return e;
+  };
   // range stage; azimuth forward + entropy sums + adjoint azimuth transforms of the two
   // gradient fields in one kernel (written interleaved); range
   // adjoint combining the fields with the global entropy sums
-  hipError_t e = tffr::launch_fwd_rows<R>(P->geo, t, sample_type(P), smp, (const R*)ph, (const R*)da, w, hx, 1, st);
+  hipError_t e = step(hipSuccess);
+  if (e == hipSuccess)
+    e = tffr::launch_fwd_rows<R>(P->geo, t, sample_type(P), smp, (const R*)ph, (const R*)da, w, hx, 1, st);
   // few partial sums: every adjoint block reduces them itself (no separate launch)
   const bool fuse = nparts <= kFuseStatsMax;
-  if (!P->ent_fused) {  // the fused azimuth kernel's LDS does not fit: image round trip
-    if (e == hipSuccess) e = tffr::launch_fwd_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, part, st);
-    if (e == hipSuccess && !fuse) e = tffr::launch_entropy_stats(part, nparts, stats, loss, st);
-    if (e == hipSuccess)
+  if (!P->ent_fused) {  // image round trip: forward azimuth stage, then the adjoint one
+    if ((e = step(e)) == hipSuccess) e = tffr::launch_fwd_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, part, st);
+    if (!fuse && (e = step(e)) == hipSuccess) e = tffr::launch_entropy_stats(part, nparts, stats, loss, st);
+    if ((e = step(e)) == hipSuccess)
       e = fuse ? tffr::launch_adj_cols<R>(P->geo, t, P->cb, (const cplx<R>*)img, hx, nullptr, part, nparts, loss, st)
                : tffr::launch_adj_cols<R>(P->geo, t, P->cb, (const cplx<R>*)img, hx, stats, nullptr, 0, nullptr, st);
-    if (e == hipSuccess)
+    if ((e = step(e)) == hipSuccess)
       e = tffr::launch_adj_rows<R>(P->geo, t, sample_type(P), hx, smp, (const R*)ph, (const R*)da, w, (cplx<R>*)gs,
                                    (R*)gph, (R*)gda, tffr::EntComb<R>{}, st);
-    return hip_status(e);
+  } else {
+    if ((e = step(e)) == hipSuccess)
+      e = tffr::launch_ent_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, part, cblk, h12, st);
+    if (!fuse && (e = step(e)) == hipSuccess) e = tffr::launch_entropy_stats(part, nparts, stats, loss, st);
+    if ((e = step(e)) == hipSuccess) e = launch_ent_adj_rows<R>(P, smp, ph, da, w, loss, gs, gph, gda, work, st);
   }
-  if (e == hipSuccess) e = tffr::launch_ent_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, part, cblk, h12, st);
-  if (e == hipSuccess && !fuse) e = tffr::launch_entropy_stats(part, nparts, stats, loss, st);
-  if (e == hipSuccess) e = launch_ent_adj_rows<R>(P, smp, ph, da, w, loss, gs, gph, gda, work, st);
+  if (e == hipSuccess && mark) e = mark(mark_ctx, k);
+  if (nk) *nk = k;
   return hip_status(e);
+}
+
+// Launch names of the step, in order, for tffr_debug_step_kernel_times.
+int step_kernel_names(const tffr_plan* P, const char** names) {
+  const int nparts = (P->prm.mx + P->cb - 1) / P->cb;
+  int k = 0;
+  names[k++] = P->geo.range_mode == 1 ? "k_fwd_rows_run" : "k_fwd_rows";
+  if (!P->ent_fused) {
+    names[k++] = "k_fwd_cols";
+    if (nparts > kFuseStatsMax) names[k++] = "k_entropy_stats";
+    names[k++] = "k_adj_cols";
+  } else {
+    names[k++] = "k_ent_cols";
+    if (nparts > kFuseStatsMax) names[k++] = "k_entropy_stats";
+  }
+  names[k++] = "k_adj_rows";
+  return k;
+}
+
+struct EventMarks {
+  hipEvent_t ev[8];
+  hipStream_t st;
+};
+hipError_t record_mark(void* ctx, int i) {
+  EventMarks* m = (EventMarks*)ctx;
+  return hipEventRecord(m->ev[i], m->st);
 }
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -999,6 +1039,40 @@ tffr_status tffr_debug_ent_adj_rows(tffr_plan* P, const void* smp, const void* p
     e = launch_ent_adj_rows<float>(P, smp, ph, da, w, loss, gs, gph, gda, work, st);
   }
   return hip_status(e);
+}
+
+tffr_status tffr_debug_step_kernel_times(tffr_plan* P, const void* smp, const void* ph, const void* da, const void* uw,
+                                         void* img, double* loss, void* gs, void* gph, void* gda, void* work,
+                                         tffr_stream stream, int32_t nsteps, float* ms_out, int32_t* nkern,
+                                         const char** names) {
+  if (!P || !smp || !img || !loss || !gs || !work || !ms_out || !nkern || nsteps < 1) return TFFR_ERR_ARG;
+  if (P->prm.weighting == TFFR_W_USER && !uw) return TFFR_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  EventMarks m{};
+  m.st = st;
+  int created = 0;
+  hipError_t e = hipSuccess;
+  for (; created < 8 && e == hipSuccess; ++created) e = hipEventCreate(&m.ev[created]);
+  if (e != hipSuccess) --created;
+  std::vector<double> acc(7, 0.0);
+  int nk = 0;
+  tffr_status s = e == hipSuccess ? TFFR_OK : TFFR_ERR_HIP;
+  for (int it = 0; it < nsteps && s == TFFR_OK; ++it) {
+    s = P->dbl() ? do_entropy_step<double>(P, smp, ph, da, uw, img, loss, gs, gph, gda, work, st, record_mark, &m, &nk)
+                 : do_entropy_step<float>(P, smp, ph, da, uw, img, loss, gs, gph, gda, work, st, record_mark, &m, &nk);
+    if (s == TFFR_OK && hipEventSynchronize(m.ev[nk]) != hipSuccess) s = TFFR_ERR_HIP;
+    for (int i = 0; i < nk && s == TFFR_OK; ++i) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, m.ev[i], m.ev[i + 1]) != hipSuccess) s = TFFR_ERR_HIP;
+      acc[i] += ms;
+    }
+  }
+  for (int i = 0; i < created; ++i) (void)hipEventDestroy(m.ev[i]);
+  if (s != TFFR_OK) return s;
+  for (int i = 0; i < nk; ++i) ms_out[i] = (float)(acc[i] / nsteps);
+  *nkern = nk;
+  if (names) step_kernel_names(P, names);
+  return TFFR_OK;
 }
 
 tffr_status tffr_debug_plan_config(const tffr_plan* P, int32_t* range_mode, int32_t* az_cols, int32_t* ent_fused) {

@@ -66,8 +66,11 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(Geo g, Tab<R> t, int stype, con
             if (p < pb) {
               const double kx = kx_of(t, kr[j], ku);
               const double lam = lattice_coord(kx, g);
-              const cplx<R> c = weighted_sample<R>(g, t, poly, stype, samples, w, n, p, ku, lam, rot, sr[j]);
-              if (g.literal) {
+              bool kept;
+              const cplx<R> c = weighted_sample<R>(g, t, poly, stype, samples, w, n, p, ku, lam, rot, sr[j], kept);
+              if (!kept) {
+                // removed by the threshold: no taps
+              } else if (g.literal) {
                 lit_spread<R>(buf, N, kx * g.tx_scale, g.q, g.lit_taps, g.a, g.ema2, c);
               } else {
                 int ui;
@@ -176,7 +179,8 @@ __global__ __launch_bounds__(NT) void k_fwd_rows_run(Geo g, Tab<R> t, int stype,
       }
       const double kx = kx_of(t, kp, ku);
       const double lam = lattice_coord(kx, g);
-      const cplx<R> c = weighted_sample<R>(g, t, poly, stype, samples, w, n, p, ku, lam, rot, sp);
+      bool kept;
+      const cplx<R> c = weighted_sample<R>(g, t, poly, stype, samples, w, n, p, ku, lam, rot, sp, kept);
       const double tt = kx * g.tx_scale;
       int ui;
       R f;
@@ -184,7 +188,8 @@ __global__ __launch_bounds__(NT) void k_fwd_rows_run(Geo g, Tab<R> t, int stype,
       const int k0 = (int)ceil(f - halfw);
       // unwrapped first tap cell (only differences and the low LOGN bits are used)
       const int c0 = (int)((unsigned)(int)floor(tt) * (unsigned)N + (unsigned)(ui + k0));
-      if (p == p0) base = cfirst = c0;
+      if (p == p0) base = cfirst = c0;  // the run's lead region starts at its first sample
+      if (!kept) continue;  // removed by the threshold: the next kept sample retires the gap
       for (int adv = c0 - base; adv > 0; --adv) retire();
       const R z0 = ((R)k0 - f) * inv_halfw;
 #pragma unroll
@@ -311,8 +316,12 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
       if (w && !ffr) w_next = w[base + p_next];
     }
     const double kx = kx_of(t, kp, ku);
+    // diagonal weight first: a sample the threshold removes needs no gather
+    const R wt = ffr ? (R)1 : (w ? wp : diag_weight<R>(g, t, poly, ku, n, p, lattice_coord(kx, g)));
     cplx<R> a = {0, 0};
-    if (g.literal) {
+    if (wt == (R)0) {
+      // removed by the threshold: zero gradient
+    } else if (g.literal) {
       a = lit_gather<R>(buf, N, kx * g.tx_scale, g.q, g.lit_taps, g.a, g.ema2);
     } else {
       int ui;
@@ -330,7 +339,6 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
       gbuf[p] = a;
       continue;
     }
-    const R wt = w ? wp : diag_weight<R>(g, t, poly, ku, n, p, lattice_coord(kx, g));
     const cplx<R> gs = cmulc(wt * a, rot);  // exp(-i psi) D^T A^H
     grad_s[base + p] = gs;
     if (want_phase) acc_phase += (double)gs.y * (double)sp.x - (double)gs.x * (double)sp.y;

@@ -8,6 +8,20 @@
         plain copy kernel (__amd_rocclr_copyBuffer) of known size the run also launched;
         prints key: value lines that bench.py reads back (with the kernel-source hash, so a
         changed kernel is not reported with stale counters).
+    python -m paper_1910_10908_amd.profiling counters <pmc dir> [<pmc dir> ...] --kernel NAME
+        per-dispatch means of every SQ / GRBM counter the runs collected for kernel NAME,
+        and the compute ceilings they give (same key: value format):
+        with C = the dispatch's duration (its trace timestamps) times the published 2.4 GHz
+        clock, the fraction of each unit's peak the kernel used:
+          valu_busy   = SQ_ACTIVE_INST_VALU / (CUs * C)   (quad-cycles per CU-cycle: the share
+                        of SIMD cycles issuing vector ALU work)
+          valu_issue  = 4 (SQ_INSTS_VALU + 3 SQ_INSTS_VALU_TRANS_F32 + 3 SQ_INSTS_VALU_TRANS_F64)
+                        / (4 CUs * C)   (wave64 instructions at 4 cycles each on a 16-lane SIMD,
+                        transcendentals at a quarter rate)
+          lds_util    = SQ_LDS_IDX_ACTIVE / (CUs * C)   (LDS busy share per CU)
+          lds_conflict_share = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE
+          occupancy   = 4 SQ_WAVE_CYCLES / (32 CUs * C)  (resident waves over the 32 slots)
+          gui_clock_GHz = GRBM_GUI_ACTIVE / 8 / duration (the CSV sums the 8 XCDs)
 """
 
 import argparse
@@ -106,6 +120,60 @@ def read_traffic(path):
     return out
 
 
+CU_NUM = 256
+XCD_NUM = 8
+PEAK_CLOCK_GHZ = 2.4
+
+
+def counters(dirs, kernel):
+    """Per-dispatch means of the counters in one or more --pmc runs for kernel NAME, and the
+    derived compute fractions (see the module docstring)."""
+    vals = {}
+    for d in dirs:
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise FileNotFoundError(f"no counter_collection.csv under {d}")
+        per = collections.defaultdict(lambda: collections.defaultdict(float))
+        dur = {}
+        for r in csv.DictReader(open(files[0])):
+            if kernel not in _short(r["Kernel_Name"]):
+                continue
+            per[r["Counter_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+            dur[r["Dispatch_Id"]] = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+            for key in ("VGPR_Count", "SGPR_Count", "LDS_Block_Size", "Workgroup_Size", "Grid_Size", "Scratch_Size"):
+                vals.setdefault(key, float(r[key]))
+        for cname, disp in per.items():
+            v = sum(disp.values()) / len(disp)
+            # GRBM_GUI_ACTIVE is collected in every pass: keep the first
+            vals.setdefault(cname, v)
+        if dur:
+            vals.setdefault("dispatch_ns", sum(dur.values()) / len(dur))
+    if not vals:
+        raise KeyError(f"{kernel}: no dispatches")
+    out = {"kernel": kernel}
+    out.update({k: vals[k] for k in sorted(vals)})
+    # capacity: the kernel's dispatch duration at the published 2.4 GHz clock (the peak the
+    # fractions are quoted against).  The CSV's GRBM_GUI_ACTIVE sums the 8 XCDs' graphics
+    # blocks; an eighth of it over the duration is the clock the kernel actually ran at.
+    cyc = vals.get("dispatch_ns", 0.0) * PEAK_CLOCK_GHZ
+    if vals.get("GRBM_GUI_ACTIVE") and vals.get("dispatch_ns"):
+        out["gui_clock_GHz"] = vals["GRBM_GUI_ACTIVE"] / XCD_NUM / vals["dispatch_ns"]
+    if cyc:
+        if "SQ_ACTIVE_INST_VALU" in vals:
+            out["valu_busy"] = vals["SQ_ACTIVE_INST_VALU"] / (CU_NUM * cyc)
+        if "SQ_INSTS_VALU" in vals:
+            trans = vals.get("SQ_INSTS_VALU_TRANS_F32", 0.0) + vals.get("SQ_INSTS_VALU_TRANS_F64", 0.0)
+            out["valu_issue"] = 4.0 * (vals["SQ_INSTS_VALU"] + 3.0 * trans) / (4.0 * CU_NUM * cyc)
+        if "SQ_LDS_IDX_ACTIVE" in vals:
+            out["lds_util"] = vals["SQ_LDS_IDX_ACTIVE"] / (CU_NUM * cyc)
+            if vals["SQ_LDS_IDX_ACTIVE"] > 0 and "SQ_LDS_BANK_CONFLICT" in vals:
+                out["lds_conflict_share"] = vals["SQ_LDS_BANK_CONFLICT"] / vals["SQ_LDS_IDX_ACTIVE"]
+        if "SQ_WAVE_CYCLES" in vals:
+            out["occupancy"] = 4.0 * vals["SQ_WAVE_CYCLES"] / (32.0 * CU_NUM * cyc)
+    out["source_hash"] = kernel_source_hash()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -117,9 +185,15 @@ def main(argv=None):
     p.add_argument("write_dir")
     p.add_argument("--kernel", required=True)
     p.add_argument("--copy-bytes", type=int, default=COPY_BYTES)
+    c = sub.add_parser("counters")
+    c.add_argument("dirs", nargs="+")
+    c.add_argument("--kernel", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         print(trace_summary(a.dir, a.only))
+    elif a.cmd == "counters":
+        for k, v in counters(a.dirs, a.kernel).items():
+            print(f"{k}: {v}")
     else:
         for k, v in traffic(a.fetch_dir, a.write_dir, a.kernel, a.copy_bytes).items():
             print(f"{k}: {v}")

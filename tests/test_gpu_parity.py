@@ -195,7 +195,7 @@ def test_adjoint_parity(size, dtype, width, weighting):
     e3 = np.max(np.abs(gda.cpu().numpy() - rgda)) / np.max(np.abs(rgda))
     print(f"  grad_s rel-L2 {e1:.3e}  dphi {e2:.3e}  ddu {e3:.3e}", flush=True)
     tol = tol_for(case)
-    assert e1 < tol and e2 < 20 * tol and e3 < 20 * tol
+    assert e1 < tol and e2 < tol and e3 < tol
 
 
 @pytest.mark.parametrize("dtype,width", [(T.C64, 7), (T.C128, 14)])
@@ -212,7 +212,7 @@ def test_ffr_forward_adjoint(dtype, width):
     gs, gph, _ = case.plan.tffr_adjoint(yt, st, case.real(phase), want_phase=True)
     rgs, rgph, _ = OP.backward(case.prob, yt.cpu().numpy().astype(np.complex128), s, case.rounded(phase))
     assert rel_l2(gs.cpu().numpy(), rgs) < tol_for(case)
-    assert np.max(np.abs(gph.cpu().numpy() - rgph)) < 20 * tol_for(case) * np.max(np.abs(rgph))
+    assert np.max(np.abs(gph.cpu().numpy() - rgph)) < tol_for(case) * np.max(np.abs(rgph))
     # the explicit weights of tffr_weights give the same image as the plan's cached D
     D = case.plan.tffr_weights()
     got2 = case.plan.tffr_forward(st, case.real(phase), user_w=D).cpu().numpy()
@@ -247,9 +247,9 @@ def test_entropy_and_gradients():
     assert abs(float(loss) - OE.entropy(ref_img)) < 1e-5 * abs(OE.entropy(ref_img))
     gI = OE.entropy_grad(ref_img)
     rgs, rgph, rgda = OP.backward(case.prob, gI, s, case.rounded(phase), case.rounded(dal))
-    assert rel_l2(st.grad.cpu().numpy(), rgs) < 1e-4
-    assert np.max(np.abs(pt.grad.cpu().numpy() - rgph)) < 1e-4 * np.max(np.abs(rgph))
-    assert np.max(np.abs(dt.grad.cpu().numpy() - rgda)) < 1e-4 * np.max(np.abs(rgda))
+    assert rel_l2(st.grad.cpu().numpy(), rgs) < 1e-5
+    assert np.max(np.abs(pt.grad.cpu().numpy() - rgph)) < 1e-5 * np.max(np.abs(rgph))
+    assert np.max(np.abs(dt.grad.cpu().numpy() - rgda)) < 1e-5 * np.max(np.abs(rgda))
     # a global phase leaves |I| unchanged
     assert abs(float(pt.grad.double().sum())) < 1e-4 * float(pt.grad.double().abs().sum())
 
@@ -320,9 +320,9 @@ def test_entropy_step_matches_separate_calls_and_oracle(dtype, width):
     assert rel_l2(img.cpu().numpy(), ref_img) < tol
     assert abs(float(loss) - OE.entropy(ref_img)) < 10 * tol * abs(OE.entropy(ref_img))
     rgs, rgph, rgda = OP.backward(case.prob, OE.entropy_grad(ref_img), s, case.rounded(phase), case.rounded(dal))
-    assert rel_l2(gs.cpu().numpy(), rgs) < 20 * tol
-    assert np.max(np.abs(gph.cpu().numpy() - rgph)) < 20 * tol * np.max(np.abs(rgph))
-    assert np.max(np.abs(gda.cpu().numpy() - rgda)) < 20 * tol * np.max(np.abs(rgda))
+    assert rel_l2(gs.cpu().numpy(), rgs) < tol
+    assert np.max(np.abs(gph.cpu().numpy() - rgph)) < tol * np.max(np.abs(rgph))
+    assert np.max(np.abs(gda.cpu().numpy() - rgda)) < tol * np.max(np.abs(rgda))
 
 
 @pytest.mark.parametrize("weighting", [T.W_TFFR, T.W_FFR])
@@ -409,7 +409,7 @@ def test_plan_from_jittered_coordinates_vs_oracle(weighting):
     e2 = np.max(np.abs(gph.cpu().numpy() - rgph)) / np.max(np.abs(rgph))
     e3 = np.max(np.abs(gda.cpu().numpy() - rgda)) / np.max(np.abs(rgda))
     print(f"  forward {e:.3e}  grad_s {e1:.3e}  dphi {e2:.3e}  ddu {e3:.3e}", flush=True)
-    assert e < 1e-5 and e1 < 1e-5 and e2 < 2e-4 and e3 < 2e-4
+    assert e < 1e-5 and e1 < 1e-5 and e2 < 1e-5 and e3 < 1e-5
 
 
 @pytest.mark.parametrize("dtype", [T.C64, T.C128, T.C64_FP16IN])
