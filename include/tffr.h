@@ -54,7 +54,7 @@ typedef enum {
   TFFR_ERR_NONMONOTONE = 3,  /* k (or kx along a slice) is not strictly increasing  */
   TFFR_ERR_LAYOUT = 4,       /* buffer misaligned, or ky not constant along a slice  */
   TFFR_ERR_UNSUPPORTED = 5,  /* width, dtype, grid size or FFR band not supported   */
-  TFFR_ERR_SINGULAR = 6,     /* plain-FFR frame product has a vanishing pivot       */
+  TFFR_ERR_SINGULAR = 6,     /* plain-FFR solve numerically singular in FP64        */
   TFFR_ERR_NOMEM = 7,        /* device or host allocation of plan tables failed     */
   TFFR_ERR_HIP = 8,          /* a HIP runtime call failed                           */
   TFFR_ERR_SCRATCH = 9       /* tffr_entropy_step_noalloc: the plan's step needs more
@@ -119,8 +119,16 @@ tffr_status tffr_validate(const tffr_params *p, const double *k, const double *k
 
 /* Create a plan on the current HIP device.  k and ku are copied.  Builds the device
  * tables (kernel deapodisation, twiddles, per-slice azimuth taps, tFFR weight
- * polynomial) and, for TFFR_W_FFR, checks that the band fits (TFFR_ERR_UNSUPPORTED).
- * Synchronises the device once.  *out is NULL on error. */
+ * polynomial).  For TFFR_W_FFR it also solves the plain-FFR weights of every slice on
+ * the device and keeps them (Eq. (8)): by selected inversion of the banded frame product
+ * when no slice has more samples than lattice points (and the band, widened to r, is at
+ * most 8), or, when every slice has more samples than lattice points (the product has
+ * rank L < P), of the product of the factors' Gram matrices, pinv(A B^T) = B (B^T B)^-1
+ * (A^T A)^-1 A^T (q <= 3, r times the widest sample spacing plus 2q at most 10); any
+ * other geometry gives TFFR_ERR_UNSUPPORTED, and a slice whose matrix is numerically
+ * singular in FP64 (a vanishing block pivot, or an inverse of 1e15 or more over the
+ * matrix scale after diagonal equilibration) gives TFFR_ERR_SINGULAR.  Synchronises the
+ * device.  *out is NULL on error. */
 tffr_status tffr_plan_create(const tffr_params *p, const double *k, const double *ku,
                              tffr_plan **out);
 

@@ -41,6 +41,18 @@ tffr_status tffr_debug_cols(tffr_plan *plan, const void *d_hx, void *d_image, tf
 tffr_status tffr_debug_plan_config(const tffr_plan *plan, int32_t *range_mode, int32_t *az_cols,
                                    int32_t *ent_fused);
 
+/* Plain-FFR solve route of a TFFR_W_FFR plan: route 0 when every slice has no more samples
+ * than lattice points (selected inversion of the frame product), 1 when every slice has
+ * more (selected inversion of Sa Sb, the factors' Gram matrices); lattice_max the most
+ * lattice points of a slice (plus a margin of 2); solve_status the outcome of the
+ * plan-time solve: 0 ok, 1 a vanishing block pivot, 3 an inverse beyond 1e15 of the
+ * matrix scale, 2 a slice reaching more lattice points than provided for.  Plan creation
+ * fails on a nonzero status unless the environment sets TFFR_FFR_KEEP_SINGULAR=1 (then
+ * the plan is kept for inspection and its weights are zero on the failed slices).  Any
+ * pointer may be NULL.  TFFR_ERR_ARG for other weightings. */
+tffr_status tffr_debug_ffr_route(const tffr_plan *plan, int32_t *route, int32_t *lattice_max,
+                                 int32_t *solve_status);
+
 /* Azimuth stage of the fused entropy step alone (the launch inside tffr_entropy_step):
  *   d_hx     [n_pulses][mx] range spectra, read only
  *   d_image  [mx][my] written (as tffr_debug_cols)

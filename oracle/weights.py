@@ -143,8 +143,11 @@ def pinv(G, band=None):
     factorisation with partial pivoting (LAPACK's banded one when G vanishes beyond `band`
     diagonals, the frame products being banded) and used when the 1-norm condition number
     ||G|| ||G^-1|| stays below 1e12 (the products of slices whose samples are more than a
-    lattice unit apart have 2-3); otherwise the SVD-based numpy.linalg.pinv with its
-    default cut-off.
+    lattice unit apart have 2-3).  Otherwise the SVD pseudo-inverse, keeping the singular
+    values above max(M, N) eps sigma_max (the usual numerical-rank cut-off): a product of
+    rank L < P computed in FP64 carries P - L singular values of rounding size (~1e-15
+    sigma_max), which the exact pseudo-inverse does not have and which numpy's fixed
+    1e-15 default would invert.
     """
     from scipy.linalg import lapack
 
@@ -168,7 +171,7 @@ def pinv(G, band=None):
             Z = Z if info == 0 else None
     if Z is not None and np.all(np.isfinite(Z)) and np.linalg.norm(G, 1) * np.linalg.norm(Z, 1) < 1e12:
         return Z
-    return np.linalg.pinv(G)
+    return np.linalg.pinv(G, rtol=max(G.shape) * np.finfo(np.float64).eps)
 
 
 def ffr_weights_row(lam_row, a=0.01, q=3.0, r=2):

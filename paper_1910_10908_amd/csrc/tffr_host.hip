@@ -21,7 +21,6 @@ namespace {
 
 constexpr double kPi = 3.141592653589793;
 constexpr int kMaxLogN = 14;
-constexpr int kMaxHalfBand = 6;
 constexpr int kPartials = 1024;  // reduction blocks for the kept count
 constexpr int kEntropyParts = 256;  // reduction blocks for the entropy
 constexpr int kFuseStatsMax = 1024;  // entropy step: adjoint blocks reduce up to this many partials
@@ -163,6 +162,10 @@ struct tffr_plan {
   tffr::Geo geo{};
   int cb = 1;  // range columns per workgroup in the azimuth stage
   int ffr_halfband = 0;
+  int ffr_route = 0;  // plain FFR: 0 selected inversion of the frame product, 1 of Sa Sb
+  int ffr_lmax = 0;   // plain FFR: most lattice points of a slice
+  int ffr_nwg = 0;    // plain FFR: workgroups of the solve (each with its own scratch)
+  int ffr_status = 0; // plain FFR: outcome of the plan-time solve (0 ok, 1 pivot, 3 conditioning, 2 lattice)
   double beta = 0.0;
   // device tables
   DevBuf k, ku, kx, ky, ystart, ytap, deapx, deapy, twx, twy, poly, ffr_d, ycn, ycw;
@@ -320,6 +323,43 @@ int ffr_halfband(const tffr_params* p, const HostKx& kx) {
     }
   }
   return b + 1;
+}
+
+// Plain-FFR route (see tffr_ffr.hip).  Route 0: every slice has no more samples than
+// lattice points (the frame product can have full rank) and its half-band, widened to r,
+// is at most 8: selected inversion of the product itself.  Route 1: every slice has more
+// samples than lattice points (rank-deficient product, full-rank factors), q <= 3 and
+// r times the largest sample spacing plus 2q at most 10 (the lattice offsets the band of
+// D reaches within the half-band 10 of Sa Sb): selected inversion of Sa Sb.  Anything
+// else is TFFR_ERR_UNSUPPORTED.  lmax: the most lattice points of a slice.
+constexpr int kFfrDirectMaxBand = 8;
+constexpr int kFfrNormalBand = 10;
+tffr_status ffr_route(const tffr_params* p, const HostKx& kx, int* route, int* hb_out, int* lmax_out) {
+  const int P = p->n_freq;
+  int n_full = 0, n_def = 0, lmax = 0;
+  double spmax = 0.0;
+  std::vector<double> lam(P);
+  for (int n = 0; n < p->n_pulses; ++n) {
+    for (int i = 0; i < P; ++i) lam[i] = kx(n, i) * p->fov_x / (2.0 * kPi);
+    for (int i = 0; i + 1 < P; ++i) spmax = std::max(spmax, lam[i + 1] - lam[i]);
+    const int l0 = (int)std::floor(lam[0] - p->q) + 1;
+    const int L = (int)(std::ceil(lam[P - 1] + p->q) - 1.0) - l0 + 1;
+    lmax = std::max(lmax, L);
+    if (P <= L) ++n_full; else ++n_def;
+  }
+  const int hb = ffr_halfband(p, kx);
+  *hb_out = hb;
+  *lmax_out = lmax + 2;  // margin: the kernels round the lattice coordinate in their own order
+  if (p->q > 4.0) return TFFR_ERR_UNSUPPORTED;  // at most 2 (ceil(q) + 1) + 1 = 11 lattice taps
+  if (n_def == 0 && std::max(hb, p->band_r) <= kFfrDirectMaxBand) {
+    *route = 0;
+    return TFFR_OK;
+  }
+  if (n_full == 0 && p->q <= 3.0 && p->band_r * spmax + 2.0 * p->q <= (double)kFfrNormalBand) {
+    *route = 1;
+    return TFFR_OK;
+  }
+  return TFFR_ERR_UNSUPPORTED;
 }
 
 }  // namespace
@@ -557,8 +597,10 @@ tffr_status tffr_validate(const tffr_params* p, const double* k, const double* k
   for (int i = 0; i < p->n_freq; ++i) kmin = std::min(kmin, std::fabs(k[i]));
   for (int i = 0; i < p->n_pulses; ++i) kumax = std::max(kumax, std::fabs(ku[i]));
   if (!(4.0 * (kmin * kmin) - kumax * kumax > 0.0)) return TFFR_ERR_EVANESCENT;
-  if (p->weighting == TFFR_W_FFR && ffr_halfband(p, HostKx{k, ku, nullptr, p->n_freq}) > kMaxHalfBand)
-    return TFFR_ERR_UNSUPPORTED;
+  if (p->weighting == TFFR_W_FFR) {
+    int route, hb, lmax;
+    return ffr_route(p, HostKx{k, ku, nullptr, p->n_freq}, &route, &hb, &lmax);
+  }
   return TFFR_OK;
 }
 
@@ -577,8 +619,10 @@ tffr_status tffr_validate_xy(const tffr_params* p, const double* kx, const doubl
       if (!(r[i] > r[i - 1])) return TFFR_ERR_NONMONOTONE;
     }
   }
-  if (p->weighting == TFFR_W_FFR && ffr_halfband(p, HostKx{nullptr, nullptr, kx, p->n_freq}) > kMaxHalfBand)
-    return TFFR_ERR_UNSUPPORTED;
+  if (p->weighting == TFFR_W_FFR) {
+    int route, hb, lmax;
+    return ffr_route(p, HostKx{nullptr, nullptr, kx, p->n_freq}, &route, &hb, &lmax);
+  }
   return TFFR_OK;
 }
 
@@ -767,15 +811,17 @@ tffr_status plan_create(const tffr_params* p, const double* k, const double* ku,
   P->off_status = off;
   off = align_up(off + sizeof(int));
   if (p->weighting == TFFR_W_FFR) {
-    P->ffr_halfband = ffr_halfband(p, hkx);
-    // the selected inversion yields the inverse on the band it factors; B_r may reach
-    // beyond the frame product's own half-band, so factor with the wider of the two
-    g.band_b = std::max(P->ffr_halfband, p->band_r);
-    if ((size_t)p->n_freq * (2 * g.band_b + 1) * sizeof(double) > lds_max) return fail(TFFR_ERR_UNSUPPORTED);
-    const size_t N = (size_t)p->n_pulses * p->n_freq;
+    s = ffr_route(p, hkx, &P->ffr_route, &P->ffr_halfband, &P->ffr_lmax);
+    if (s != TFFR_OK) return fail(s);
+    // route 0: the selected inversion yields the inverse on the band it factors; B_r may
+    // reach beyond the frame product's own half-band, so factor with the wider of the two
+    g.band_b = P->ffr_route == 0 ? std::max(P->ffr_halfband, p->band_r) : kFfrNormalBand;
     const size_t KT = 2 * ((size_t)std::ceil(p->q) + 1) + 1;
-    P->off_gband = off;  // FFR scratch: tap tables, floors, band, LU factors
-    off = align_up(off + N * (2 * KT + (2 * g.band_b + 1)) * sizeof(double) + N * sizeof(int));
+    if (P->ffr_route == 0 && (size_t)p->n_freq * (KT * sizeof(double) + sizeof(int)) > lds_max)
+      return fail(TFFR_ERR_UNSUPPORTED);
+    P->ffr_nwg = std::min(p->n_pulses, P->ffr_route == 0 ? 1024 : 512);
+    P->off_gband = off;  // FFR scratch: per-workgroup bands, Gram matrices and reduction blocks
+    off = align_up(off + tffr::ffr_scratch_bytes(g, P->ffr_route, P->ffr_lmax, P->ffr_nwg));
   }
   P->work_bytes = off;
 
@@ -789,17 +835,19 @@ tffr_status plan_create(const tffr_params* p, const double* k, const double* ku,
     hipError_t e = hipMemset(wb + P->off_status, 0, sizeof(int));
     if (e == hipSuccess) {
       if (P->dbl())
-        e = tffr::launch_ffr<double>(g, tables<double>(P), (double*)(wb + P->off_gband), (double*)P->ffr_d.p,
-                                     (int*)(wb + P->off_status), 0);
+        e = tffr::launch_ffr<double>(g, tables<double>(P), P->ffr_route, P->ffr_lmax, P->ffr_nwg,
+                                     (double*)(wb + P->off_gband), (double*)P->ffr_d.p, (int*)(wb + P->off_status), 0);
       else
-        e = tffr::launch_ffr<float>(g, tables<float>(P), (double*)(wb + P->off_gband), (float*)P->ffr_d.p,
-                                    (int*)(wb + P->off_status), 0);
+        e = tffr::launch_ffr<float>(g, tables<float>(P), P->ffr_route, P->ffr_lmax, P->ffr_nwg,
+                                    (double*)(wb + P->off_gband), (float*)P->ffr_d.p, (int*)(wb + P->off_status), 0);
     }
     int st = 0;
     if (e == hipSuccess) e = hipMemcpy(&st, wb + P->off_status, sizeof(int), hipMemcpyDeviceToHost);
     (void)hipFree(work);
     if (e != hipSuccess) return fail(TFFR_ERR_HIP);
-    if (st != 0) return fail(TFFR_ERR_SINGULAR);
+    P->ffr_status = st;
+    const char* keep = std::getenv("TFFR_FFR_KEEP_SINGULAR");  // diagnostics: keep the plan, query the status
+    if (st != 0 && !(keep && std::atoi(keep) == 1)) return fail(st == 2 ? TFFR_ERR_LAYOUT : TFFR_ERR_SINGULAR);
   }
   if (hipDeviceSynchronize() != hipSuccess) return fail(TFFR_ERR_HIP);
   P->scratch = scratch_for_device(P->device);  // device current: the plan's
@@ -951,10 +999,10 @@ tffr_status tffr_weights(tffr_plan* P, void* d_w, void* work, tffr_stream stream
   hipError_t e;
   if (P->prm.weighting == TFFR_W_FFR) {
     int* status = (int*)(wb + P->off_status);
-    e = P->dbl() ? tffr::launch_ffr<double>(P->geo, tables<double>(P), (double*)(wb + P->off_gband), (double*)d_w,
-                                            status, st)
-                 : tffr::launch_ffr<float>(P->geo, tables<float>(P), (double*)(wb + P->off_gband), (float*)d_w,
-                                           status, st);
+    e = P->dbl() ? tffr::launch_ffr<double>(P->geo, tables<double>(P), P->ffr_route, P->ffr_lmax, P->ffr_nwg,
+                                            (double*)(wb + P->off_gband), (double*)d_w, status, st)
+                 : tffr::launch_ffr<float>(P->geo, tables<float>(P), P->ffr_route, P->ffr_lmax, P->ffr_nwg,
+                                           (double*)(wb + P->off_gband), (float*)d_w, status, st);
   } else {
     unsigned long long* kept = (unsigned long long*)(wb + P->off_kept);
     e = P->dbl() ? tffr::launch_weights<double>(P->geo, tables<double>(P), (double*)d_w, kept, kPartials, st)
@@ -1072,6 +1120,15 @@ tffr_status tffr_debug_step_kernel_times(tffr_plan* P, const void* smp, const vo
   for (int i = 0; i < nk; ++i) ms_out[i] = (float)(acc[i] / nsteps);
   *nkern = nk;
   if (names) step_kernel_names(P, names);
+  return TFFR_OK;
+}
+
+tffr_status tffr_debug_ffr_route(const tffr_plan* P, int32_t* route, int32_t* lattice_max, int32_t* solve_status) {
+  if (!P) return TFFR_ERR_ARG;
+  if (P->prm.weighting != TFFR_W_FFR) return TFFR_ERR_ARG;
+  if (route) *route = P->ffr_route;
+  if (lattice_max) *lattice_max = P->ffr_lmax;
+  if (solve_status) *solve_status = P->ffr_status;
   return TFFR_OK;
 }
 

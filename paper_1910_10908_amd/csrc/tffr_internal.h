@@ -79,7 +79,8 @@ struct EntComb {
   double* loss;
 };
 
-// Launchers (tffr_range.hip, tffr_azimuth.hip, tffr_misc.hip).  All enqueue on `st` and return the launch status.
+// Launchers (tffr_range.hip, tffr_azimuth.hip, tffr_entstep.hip, tffr_coord.hip, tffr_ffr.hip,
+// tffr_misc.hip).  All enqueue on `st` and return the launch status.
 template <typename R>
 hipError_t launch_fwd_rows(const Geo& g, const Tab<R>& t, int stype, const void* samples,
                            const R* phase, const R* dalong, const R* w, cplx<R>* out,
@@ -115,8 +116,9 @@ hipError_t launch_weights(const Geo& g, const Tab<R>& t, R* w, unsigned long lon
                           int nblocks, hipStream_t st);
 hipError_t launch_sum_u64(const unsigned long long* parts, int n, long long* out, hipStream_t st);
 template <typename R>
-hipError_t launch_ffr(const Geo& g, const Tab<R>& t, double* scratch, R* dband, int* status,
-                      hipStream_t st);
+hipError_t launch_ffr(const Geo& g, const Tab<R>& t, int route, int lmax, int nwg, double* scratch, R* dband,
+                      int* status, hipStream_t st);
+size_t ffr_scratch_bytes(const Geo& g, int route, int lmax, int nwg);  // scratch of launch_ffr
 template <typename R>
 hipError_t launch_entropy(const Geo& g, const cplx<R>* img, double* partials, int nparts,
                           double* loss, cplx<R>* grad, hipStream_t st);

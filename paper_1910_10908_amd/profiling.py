@@ -36,7 +36,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = [os.path.join(HERE, "csrc", f) for f in
                   ("tffr_device.h", "tffr_range.hip", "tffr_azimuth.hip", "tffr_entstep.hip",
-                                                  "tffr_coord.hip", "tffr_misc.hip")]
+                                                  "tffr_coord.hip", "tffr_ffr.hip", "tffr_misc.hip")]
 COPY_BYTES = 64 << 20  # the calibration copy bench.py --profile-steps launches
 
 

@@ -94,6 +94,11 @@ class Plan:
         rm, cb, fu = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _lib.check(self.lib.tffr_debug_plan_config(h, ctypes.byref(rm), ctypes.byref(cb), ctypes.byref(fu)))
         self.range_mode, self.az_cols, self.ent_fused = rm.value, cb.value, bool(fu.value)
+        self.ffr_route, self.ffr_lattice_max, self.ffr_solve_status = None, None, None
+        if params.weighting == W_FFR:
+            ro, lm, fs = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            _lib.check(self.lib.tffr_debug_ffr_route(h, ctypes.byref(ro), ctypes.byref(lm), ctypes.byref(fs)))
+            self.ffr_route, self.ffr_lattice_max, self.ffr_solve_status = ro.value, lm.value, fs.value
 
     def __del__(self):
         h = getattr(self, "handle", None)

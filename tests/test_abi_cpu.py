@@ -69,6 +69,24 @@ def test_validate_accepts_paper_geometry():
         assert T.tffr_validate(p, k, ku) == 0, wl.name
 
 
+@pytest.mark.parametrize("name,kw,code", [
+    ("ffr_vs_tffr_c64", {}, 0),                # full rank: selected inversion of the product
+    ("precision_2k", {}, 0),                   # rank deficient, spacing 0.39-0.46: Gram route
+    ("full_swath_4k", {}, 0),                  # rank deficient, spacing 0.20-0.23
+    ("autofocus_1k", {}, 0),                   # routed; its numerical singularity shows at plan time
+    ("precision_2k", dict(q=3.5), 5),          # Gram route needs q <= 3
+    ("ffr_vs_tffr_c64", dict(q=4.5), 5),       # more than 11 lattice taps per sample
+    ("ffr_vs_tffr_c64", dict(band_r=8), 0),    # band 8 still within the direct route
+])
+def test_validate_ffr_routes(name, kw, code):
+    """Host-side route choice of plain FFR: which geometries the plan can solve."""
+    wl = scenes.WORKLOADS[name]
+    k, ku = scenes.radar_sampling(wl.n_pulses, wl.n_freq)
+    p = _ok_params(n_pulses=wl.n_pulses, n_freq=wl.n_freq, mx=wl.m, my=wl.m, fov_x=wl.fov, fov_y=wl.fov,
+                   weighting=T.W_FFR, **kw)
+    assert T.tffr_validate(p, k, ku) == code
+
+
 @pytest.mark.parametrize("kw,code", [
     (dict(n_pulses=0), 1), (dict(n_freq=0), 1), (dict(mx=15), 1), (dict(my=0), 1),
     (dict(fov_x=0.0), 1), (dict(fov_y=-1.0), 1), (dict(weighting=7), 1), (dict(window_a=-0.1), 1),

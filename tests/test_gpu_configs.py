@@ -291,3 +291,59 @@ def test_correlation_threshold_bench_workload():
     e = rel_l2(got[cols], ref)
     print(f"  kept {int(kept.sum())} of {kept.size}; 16 columns rel-L2 {e:.3e}", flush=True)
     assert e < 1e-5 and peak_db(got[cols], ref) < -100
+
+
+# ---------------------------------------------------------------- plain FFR where the frame product is rank deficient
+@pytest.mark.parametrize("fov,spacing", [(50.0, "0.39-0.46 (the 2048 x 4096 spacing)"),
+                                         (25.0, "0.20-0.23 (the 4096 x 8192 spacing)")])
+@pytest.mark.parametrize("dtype", [T.C64, T.C128])
+def test_ffr_rank_deficient_vs_pseudo_inverse(fov, spacing, dtype):
+    """512 samples per slice at the dense workloads' lattice spacing: more samples than
+    lattice points, so the frame product Psi W has rank L < P.  D = B_2(pinv(Psi W)) from
+    the factored route (band of (Sa Sb)^-1 by selected inversion) against the oracle's SVD
+    pseudo-inverse of the dense product, and the image against the oracle with its own D."""
+    print(f"ffr rank-deficient, spacing {spacing}, dtype {dtype}", flush=True)
+    case = Case(12, 512, 64, fov=fov, weighting=T.W_FFR, dtype=dtype, width=7 if dtype == T.C64 else 14, seed=141)
+    assert case.plan.ffr_route == 1
+    kx, ky, lam, X, Y = case.prob.geometry()
+    assert lam.shape[1] > lam[0, -1] - lam[0, 0] + 6  # more samples than lattice points
+    D = case.plan.tffr_weights().cpu().numpy()
+    ref = OW.ffr_weights(lam, 0.01, 3.0, 2, workers=WORKERS)
+    e = _max_rel(D, ref)
+    print(f"  D max-rel {e:.2e} (max |D| {np.max(np.abs(ref)):.3e})", flush=True)
+    # Normal-equation route: the error bound grows with the condition number of Sa Sb after
+    # equilibration (~1e8 here), 1e-8 of max |D| in FP64; FP32 storage adds 6e-8.
+    assert e < (1e-7 if dtype == T.C128 else 1e-6)
+    s, st = case.samples()
+    phase = case.rng.normal(0, 0.5, 12)
+    got = case.plan.tffr_forward(st, case.real(phase)).cpu().numpy()
+    prob = OP.Problem(k=case.k, ku=case.ku, mx=64, my=64, fov_x=fov, fov_y=fov, weighting=OP.WEIGHT_USER)
+    img = OP.image(prob, s, case.rounded(phase), user_w=ref)
+    tol = 1e-7 if dtype == T.C128 else 1e-5  # the error of D above carries over
+    print(f"  image rel-L2 {rel_l2(got, img):.3e}", flush=True)
+    assert rel_l2(got, img) < tol
+
+
+@pytest.mark.parametrize("n,tol", [(1024, 1e-6), (44, 3e-5), (344, 1e-2)])
+def test_ffr_precision_workload_sampled_slices(n, tol):
+    """Plain FFR on the 2048 x 4096 geometry (4096 samples over ~1610-1850 lattice points
+    per slice): D of one slice against the oracle's SVD pseudo-inverse.  Slice 1024 is
+    well scaled (cond(A) 75).  Slice 44: its last lattice point is reached by two samples
+    with taps of 3e-3, so Sa Sb has a condition number of 4e15 (1e11 after
+    equilibration) and the product Psi W one of 6e7; the normal-equation route keeps
+    ~5 digits of max |D|.  Slice 344, the worst of the geometry: its last lattice point
+    lies 2.9996 lattice units from the only sample that reaches it (q = 3), the product's
+    condition number is 6e10 and D is not determined by FP64 arithmetic away from that
+    point (the oracle's SVD and a QR evaluation of B (B^T B)^-1 (A^T A)^-1 A^T differ by
+    O(1) in the middle of the slice); the point sets max |D| = 6.6e9, and the comparison,
+    relative to it, holds to 1e-2."""
+    wl, plan, prob = _workload_case("precision_2k", weighting=T.W_FFR)
+    assert plan.ffr_route == 1 and plan.ffr_solve_status == 0
+    D = plan.tffr_weights().cpu().numpy()
+    assert np.all(np.abs(D).reshape(wl.n_pulses, -1).max(axis=1) > 0)  # every slice solved
+    kx, ky, lam, X, Y = prob.geometry()
+    print(f"  slice {n}: oracle pseudo-inverse of the 4096 x 4096 product", flush=True)
+    ref = OW.ffr_weights(lam[n:n + 1], 0.01, 3.0, 2)[0]
+    e = _max_rel(D[n], ref)
+    print(f"  slice {n}: D max-rel {e:.2e} (max |D| {np.max(np.abs(ref)):.3e})", flush=True)
+    assert e < tol

@@ -339,14 +339,37 @@ def test_k7_band_is_band_of_pinv():
 
 
 def test_pinv_rank_deficient_falls_back_to_svd():
-    """A singular product (two equal columns) takes numpy's SVD pseudo-inverse; the
+    """A singular product (two equal columns) takes the SVD pseudo-inverse; the
     Moore-Penrose conditions hold."""
     rng = np.random.default_rng(17)
     G = rng.standard_normal((12, 12))
     G[:, 4] = G[:, 7]
     Z = weights.pinv(G)
-    assert np.max(np.abs(Z - np.linalg.pinv(G))) < 1e-13
     assert np.max(np.abs(G @ Z @ G - G)) < 1e-12 and np.max(np.abs(Z @ G @ Z - Z)) < 1e-12
+    assert np.allclose(G @ Z, (G @ Z).T, atol=1e-12) and np.allclose(Z @ G, (Z @ G).T, atol=1e-12)
+
+
+def test_pinv_of_a_rank_deficient_product_is_exact():
+    """A slice with more samples than lattice points (0.39-0.46 lattice units apart):
+    G~ = A B^T with A[p][l] = R_Psi(l - lam_p), B[p][l] = R_W(l - lam_p) of full column
+    rank L < P, so pinv(G~) = B (B^T B)^-1 (A^T A)^-1 A^T exactly (Greville).  In FP64
+    the product carries P - L singular values of rounding size (~1e-15 sigma_max); the
+    oracle's cut-off drops them and meets the closed form (whose own error is about
+    cond(A) cond(B) eps ~ 1e-12), where numpy's fixed 1e-15 default inverts some of them."""
+    k, ku = scenes.radar_sampling(4, 512)
+    kx, _ = geometry.stolt(k, ku)
+    lam = geometry.lattice_coordinate(kx, 50.0)[1]
+    ell = np.arange(int(np.floor(lam.min() - 3.0)) + 1, int(np.ceil(lam.max() + 3.0)))
+    d = ell[None, :] - lam[:, None]
+    A = np.where(np.abs(d) < 3.0, window.r_psi(d, 0.01), 0.0)
+    B = np.where(np.abs(d) < 3.0, window.r_w(d, 0.01), 0.0)
+    assert A.shape[0] > A.shape[1] and np.linalg.matrix_rank(A) == A.shape[1]
+    exact = B @ np.linalg.inv(B.T @ B) @ np.linalg.inv(A.T @ A) @ A.T
+    G = weights.frame_product_row(lam, 0.01, 3.0)
+    assert np.max(np.abs(G - A @ B.T)) < 1e-14
+    Z = weights.pinv(G, band=30)
+    assert np.max(np.abs(Z - exact)) < 1e-8 * np.max(np.abs(exact))
+    assert np.max(np.abs(np.linalg.pinv(G) - exact)) > 1.0 * np.max(np.abs(exact))
 
 
 def test_k7_frame_product_is_banded_and_near_identity():
