@@ -23,9 +23,12 @@ Frame-Based Reconstruction for Stripmap SAR"):
 * entropy    -- image entropy loss and its gradient.
 * literal    -- the range gridding of Algorithm 1 / Eq. (8) taken literally: the window's
                 own truncated transform on the image lattice, inverse DFT, division by w.
+* rma        -- the range-migration front end (azimuth transform of raw echoes and the
+                reference-function multiply, Sec. II-A) and the Stolt-interpolation
+                baseline image (Sec. II-A; Sec. IV, Baselines).
 
 Where the paper is ambiguous or garbled, the reading taken is stated in the docstring of
 the function that takes it.
 """
 
-from . import geometry, window, weights, nudft, pipeline, entropy, literal  # noqa: F401
+from . import geometry, window, weights, nudft, pipeline, entropy, literal, rma  # noqa: F401

@@ -80,6 +80,26 @@ def radar_sampling(n_pulses, n_freq, fc=10e9, bw=600e6):
     return k, ku
 
 
+def rma_positions(n_pulses, fc=10e9):
+    """Along-track sampling of the raw echoes behind radar_sampling's ku: J = 2 n_pulses
+    positions du = c / (4 fc) apart, so the J-point azimuth transform has the bin width
+    2 pi / (J du) of radar_sampling.  Returns (J, du)."""
+    return 2 * n_pulses, C_LIGHT / (4.0 * fc)
+
+
+def raw_echoes(k, n_positions, du, xc, x, y, a, chunk=16):
+    """Point-scatterer raw echoes e[j, p] = sum_t a_t exp(-2 i k_p R_t(u_j)) (FP64 numpy),
+    R_t(u) = sqrt((xc + x_t)^2 + (y_t - u)^2), u_j = (j - J/2) du."""
+    k = np.asarray(k, dtype=np.float64)
+    u = (np.arange(n_positions, dtype=np.float64) - n_positions / 2.0) * du
+    out = np.zeros((n_positions, k.size), dtype=np.complex128)
+    for t0 in range(0, len(x), chunk):
+        for t in range(t0, min(t0 + chunk, len(x))):
+            R = np.sqrt((xc + x[t]) ** 2 + (y[t] - u) ** 2)
+            out += a[t] * np.exp(-2j * np.outer(R, k))
+    return out
+
+
 def rng_for(workload_name, offset=0):
     return np.random.default_rng(SEED_BASE + WORKLOAD_ORDER.index(workload_name) + offset)
 
