@@ -412,6 +412,60 @@ def full_swath_leg(T, torch, steps):
     return rec
 
 
+def stolt_and_front_end(T, torch, wl, plan, k, ku, s, s_np, acc_cols, ms_step, args):
+    """The Stolt-interpolation baseline image and the tFFR image alone (image formation
+    only, as the paper's timing table compares), and the range-migration front end on
+    raw echoes of the same geometry (J = 2 N_u positions)."""
+    from paper_1910_10908_amd import scenes
+
+    res = {}
+    steps = max(20, args.steps // 2)
+    graph = not args.eager
+    log("comparison: stolt_interpolation, tffr image only")
+    img = torch.empty((wl.m, wl.m), dtype=torch.complex64, device=s.device)
+    ms_stolt, _ = time_step(torch, lambda: plan.tffr_stolt_image(s, out=img), steps, 5, graph=graph)
+    ms_fwd, _ = time_step(torch, lambda: plan.tffr_forward(s, out=img), steps, 5, graph=graph)
+    rec = {"ms_per_image": ms_stolt, "Msamples_per_s": wl.n_samples / (ms_stolt * 1e-3) / 1e6,
+           "tffr_image_ms": ms_fwd, "tffr_image_over_stolt": ms_fwd / ms_stolt, "over_tffr_step": ms_stolt / ms_step,
+           "note": "linear interpolation per slice onto the integer lattice, inverse FFT of the fine row, "
+                   "azimuth stage as tFFR; image formation only"}
+    if not args.no_cpu_baseline:
+        from oracle import pipeline as OP
+        from oracle import rma as ORMA
+
+        got = plan.tffr_stolt_image(s).cpu().numpy()[acc_cols].astype(np.complex128)
+        prob = OP.Problem(k=k, ku=ku, mx=wl.m, my=wl.m, fov_x=wl.fov, fov_y=wl.fov)
+        ref = ORMA.stolt_image(prob, s_np, cols=acc_cols)
+        rec["accuracy"] = dict(accuracy(got, ref), sample=f"{len(acc_cols)} of {wl.m} image columns",
+                               reference="oracle Stolt image")
+    res["stolt_interpolation"] = rec
+    log("comparison: rma_front_end")
+    J, du = scenes.rma_positions(wl.n_pulses)
+    gen = torch.Generator(s.device).manual_seed(17)
+    echoes = torch.randn((J, wl.n_freq), dtype=torch.complex64, device=s.device, generator=gen)
+    smp = torch.empty_like(s)
+    xc = 2000.0
+    ms_fe, _ = time_step(torch, lambda: plan.tffr_rma_front_end(echoes, du, xc, out=smp), steps, 5, graph=graph)
+    rec = {"ms": ms_fe, "raw_positions": J, "Msamples_per_s": wl.n_samples / (ms_fe * 1e-3) / 1e6,
+           "alg_bytes": (J + wl.n_pulses) * wl.n_freq * 8,
+           "achieved_GBps": (J + wl.n_pulses) * wl.n_freq * 8 / (ms_fe * 1e-3) / 1e9,
+           "note": "azimuth FFT of the raw echoes (J positions), centred N_u bins, reference multiply "
+                   "exp(+i kx X_c) in FP64 phase, X_c = 2 km; output samples per second"}
+    rec["hbm_frac"] = rec["achieved_GBps"] / HBM_PEAK_GBS
+    if not args.no_cpu_baseline:
+        from oracle import rma as ORMA
+
+        plan.tffr_rma_front_end(echoes, du, xc, out=smp)
+        cols = acc_cols[acc_cols < wl.n_freq]
+        ct = torch.as_tensor(cols, device=s.device)
+        ein = echoes[:, ct].cpu().numpy().astype(np.complex128)
+        ref, _ = ORMA.front_end(ein, k[cols], du, xc, wl.n_pulses)
+        rec["accuracy"] = dict(accuracy(smp[:, ct].cpu().numpy().astype(np.complex128), ref),
+                               sample=f"{len(cols)} of {wl.n_freq} fast-time columns, all pulses")
+    res["rma_front_end"] = rec
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -579,6 +633,7 @@ def main():
                                                   else "oracle exact weighted sum, tFFR weights"))
             comp[name] = rec
             del p2, st2
+        comp.update(stolt_and_front_end(T, torch, wl, plan, k, ku, s, s_np, acc_cols, ms, args))
         out["comparisons"] = comp
 
     # accuracy against the FP64 oracle on sampled image columns (and CPU timing of the oracle)

@@ -179,6 +179,31 @@ tffr_status tffr_forward(tffr_plan *plan, const void *d_samples, const void *d_p
                          const void *d_dalong, const void *d_user_w, void *d_image,
                          void *d_work, tffr_stream stream);
 
+/* Range-migration front end (Sec. II-A: frequency-domain mapping and matched filter
+ * before the Stolt change of variables):
+ *   d_echoes    [n_positions][n_freq] complex in the compute type (complex float for
+ *               TFFR_C64 and TFFR_C64_FP16IN, complex double for TFFR_C128): raw echoes
+ *               at along-track positions u_j = (j - n_positions/2) du, fast-time
+ *               wavenumbers k of the plan; read only
+ *   d_samples   [n_pulses][n_freq] samples in the plan's sample type, written:
+ *               s[n][p] = exp(+i kx[n][p] xc) sum_j e[j][p] exp(-i ku_n u_j)
+ * xc is the reference range (m) that the matched filter removes.  The plan must come
+ * from tffr_plan_create with ku_n = (n - n_pulses/2) 2 pi / (n_positions du) (checked to
+ * 1e-9 of the bin width, else TFFR_ERR_ARG); n_positions a power of two, at least 64
+ * and n_pulses (TFFR_ERR_ARG), at most 16384 (8192 for TFFR_C128; else
+ * TFFR_ERR_UNSUPPORTED).  No workspace.  Enqueued on `stream`. */
+tffr_status tffr_rma_front_end(tffr_plan *plan, const void *d_echoes, int32_t n_positions, double du,
+                               double xc, void *d_samples, tffr_stream stream);
+
+/* Stolt-interpolation baseline image (Sec. II-A; Sec. IV, Baselines): along every slice
+ * the (phased) samples are interpolated linearly onto the integer lattice l between the
+ * slice's first and last sample (kx = 2 pi l / fov_x; zero outside), and
+ *   d_image[jx][jy] = sum_n sum_l S_n(l) exp(+i (2 pi l X_jx / fov_x + ky_n Y_jy))
+ * with the pixels of tffr_forward.  The plan's weighting is not used.  Arguments as for
+ * tffr_forward (no weights).  mx must be a power of two (TFFR_ERR_UNSUPPORTED). */
+tffr_status tffr_stolt_image(tffr_plan *plan, const void *d_samples, const void *d_phase,
+                             const void *d_dalong, void *d_image, void *d_work, tffr_stream stream);
+
 /* Adjoint / backward of tffr_forward for a real loss L(I):
  *   d_grad_image   [mx][my] complex, dL/dRe I + i dL/dIm I, read only
  *   d_samples      [n_pulses][n_freq] complex (dtype); needed only when d_grad_phase or

@@ -78,11 +78,14 @@ def stolt_interpolate(s_row, lam_row):
     return l, out
 
 
-def stolt_image(prob, s, phase=None, dalong=None):
+def stolt_image(prob, s, phase=None, dalong=None, cols=None):
     """Stolt baseline image (see module doc) of the samples s [n_pulses, n_freq] of
     `prob`'s geometry, after the per-pulse phasing of the pipeline (phase, along-track
-    errors; None for none).  Range-major [mx, my] complex128."""
+    errors; None for none).  Range-major [mx, my] complex128, or only the range columns
+    `cols` [len(cols), my]."""
     kx, ky, lam, X, Y = prob.geometry()
+    if cols is not None:
+        X = X[np.asarray(cols)]
     s = np.asarray(s, dtype=np.complex128)
     psi = np.zeros(s.shape[0])
     if phase is not None:

@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libtffr.so")
 SOURCES = ["tffr_host.hip"]
 # kernel sources: one object per compute type (FP32 / FP64 instantiations), built in parallel
-KERNEL_SOURCES = ["tffr_range.hip", "tffr_azimuth.hip", "tffr_entstep.hip", "tffr_coord.hip", "tffr_ffr.hip",
+KERNEL_SOURCES = ["tffr_range.hip", "tffr_azimuth.hip", "tffr_entstep.hip", "tffr_coord.hip", "tffr_ffr.hip", "tffr_rma.hip",
                   "tffr_misc.hip"]
 ARCH = "gfx950"
 

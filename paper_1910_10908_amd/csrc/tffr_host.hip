@@ -166,6 +166,9 @@ struct tffr_plan {
   int ffr_lmax = 0;   // plain FFR: most lattice points of a slice
   int ffr_nwg = 0;    // plain FFR: workgroups of the solve (each with its own scratch)
   int ffr_status = 0; // plain FFR: outcome of the plan-time solve (0 ok, 1 pivot, 3 conditioning, 2 lattice)
+  bool from_xy = false;      // made from explicit coordinates (no Stolt map)
+  std::vector<double> hku;   // azimuth wavenumbers (host copy)
+  int stolt_part = 0;        // Stolt baseline: samples per part (span below mx - 1 lattice units)
   double beta = 0.0;
   // device tables
   DevBuf k, ku, kx, ky, ystart, ytap, deapx, deapy, twx, twy, poly, ffr_d, ycn, ycw;
@@ -377,6 +380,17 @@ tffr_status do_forward(tffr_plan* P, const void* smp, const void* ph, const void
     return hip_status(tffr::launch_fwd_rows<R>(P->geo, t, sample_type(P), smp, (const R*)ph, (const R*)da, w,
                                                (cplx<R>*)img, stage_only, st));
   hipError_t e = tffr::launch_fwd_rows<R>(P->geo, t, sample_type(P), smp, (const R*)ph, (const R*)da, w, hx, 1, st);
+  if (e == hipSuccess) e = tffr::launch_fwd_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, nullptr, st);
+  return hip_status(e);
+}
+
+template <typename R>
+tffr_status do_stolt(tffr_plan* P, const void* smp, const void* ph, const void* da, void* img, void* work,
+                     hipStream_t st) {
+  const tffr::Tab<R> t = tables<R>(P);
+  cplx<R>* hx = (cplx<R>*)((char*)work + P->off_hx);
+  hipError_t e = tffr::launch_stolt_rows<R>(P->geo, t, sample_type(P), smp, (const R*)ph, (const R*)da,
+                                            P->stolt_part, hx, st);
   if (e == hipSuccess) e = tffr::launch_fwd_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, nullptr, st);
   return hip_status(e);
 }
@@ -774,6 +788,33 @@ tffr_status plan_create(const tffr_params* p, const double* k, const double* ku,
   if (s == TFFR_OK) s = upload(P->k, kv);
   if (s == TFFR_OK) s = upload(P->kx, kxv);
   if (s == TFFR_OK) s = upload(P->ku, kuv);
+  P->from_xy = kx_tab != nullptr;
+  P->hku = kuv;
+  {
+    // Stolt baseline parts: the widest gap between consecutive samples in lattice units.
+    // On the Stolt map the gap at sample p grows with |ku| (d kx / dk = 4k / kx), so the
+    // slice of largest |ku| holds it.
+    const double lscale = p->fov_x / (2.0 * kPi);
+    double spmax = 0.0;
+    auto row_gaps = [&](int n) {
+      double prev = 0.0;
+      for (int i = 0; i < p->n_freq; ++i) {
+        const double kx = kx_tab ? kx_tab[(size_t)n * p->n_freq + i] : std::sqrt(4.0 * k[i] * k[i] - ku[n] * ku[n]);
+        if (i > 0) spmax = std::max(spmax, (kx - prev) * lscale);
+        prev = kx;
+      }
+    };
+    if (kx_tab) {
+      for (int n = 0; n < p->n_pulses; ++n) row_gaps(n);
+    } else {
+      int nmax = 0;
+      for (int n = 1; n < p->n_pulses; ++n)
+        if (std::fabs(ku[n]) > std::fabs(ku[nmax])) nmax = n;
+      row_gaps(nmax);
+    }
+    P->stolt_part =
+        spmax > 0.0 ? (int)std::max(1.0, std::min<double>(p->n_freq, std::floor((p->mx - 2) / spmax))) : p->n_freq;
+  }
   if (s == TFFR_OK) s = upload(P->ystart, ys);
   if (s == TFFR_OK) s = upload(P->ycn, cn);
   if (s != TFFR_OK) return fail(s);
@@ -899,6 +940,39 @@ tffr_status tffr_forward(tffr_plan* P, const void* smp, const void* ph, const vo
   hipStream_t st = (hipStream_t)stream;
   return P->dbl() ? do_forward<double>(P, smp, ph, da, uw, img, work, st, -1)
                   : do_forward<float>(P, smp, ph, da, uw, img, work, st, -1);
+}
+
+tffr_status tffr_rma_front_end(tffr_plan* P, const void* echoes, int32_t n_positions, double du, double xc,
+                               void* samples, tffr_stream stream) {
+  if (!P || !echoes || !samples) return TFFR_ERR_ARG;
+  if (P->from_xy || !(du > 0.0) || !std::isfinite(du) || !std::isfinite(xc)) return TFFR_ERR_ARG;
+  const int J = n_positions, NU = P->prm.n_pulses;
+  if (J < NU || J < 64 || (J & (J - 1)) != 0) return TFFR_ERR_ARG;
+  if (J > 16384 || (P->dbl() && J > 8192)) return TFFR_ERR_UNSUPPORTED;
+  // the plan's azimuth wavenumbers must be those of the J-point transform
+  const double dku = 2.0 * kPi / ((double)J * du);
+  for (int n = 0; n < NU; ++n)
+    if (std::fabs(P->hku[n] - (n - NU / 2) * dku) > 1e-9 * dku * std::max(1, NU)) return TFFR_ERR_ARG;
+  if (!aligned(echoes, P->csize() / 2) || !aligned(samples, 4)) return TFFR_ERR_LAYOUT;
+  int logj = 0;
+  while ((1 << logj) < J) ++logj;
+  hipStream_t st = (hipStream_t)stream;
+  const hipError_t e =
+      P->dbl() ? tffr::launch_rma_front<double>(P->geo, tables<double>(P), logj, (const cplx<double>*)echoes, xc,
+                                                sample_type(P), samples, st)
+               : tffr::launch_rma_front<float>(P->geo, tables<float>(P), logj, (const cplx<float>*)echoes, xc,
+                                               sample_type(P), samples, st);
+  return hip_status(e);
+}
+
+tffr_status tffr_stolt_image(tffr_plan* P, const void* smp, const void* ph, const void* da, void* img, void* work,
+                             tffr_stream stream) {
+  if (!P || !smp || !img || !work) return TFFR_ERR_ARG;
+  const int mx = P->prm.mx;
+  if ((mx & (mx - 1)) != 0 || ((1 << P->geo.lognfx) % mx) != 0) return TFFR_ERR_UNSUPPORTED;
+  if (!aligned(work, 16) || !aligned(img, P->csize() / 2) || !aligned(smp, 4)) return TFFR_ERR_LAYOUT;
+  hipStream_t st = (hipStream_t)stream;
+  return P->dbl() ? do_stolt<double>(P, smp, ph, da, img, work, st) : do_stolt<float>(P, smp, ph, da, img, work, st);
 }
 
 tffr_status tffr_adjoint(tffr_plan* P, const void* cot, const void* smp, const void* ph, const void* da, const void* uw,

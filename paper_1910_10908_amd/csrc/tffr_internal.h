@@ -123,6 +123,12 @@ template <typename R>
 hipError_t launch_entropy(const Geo& g, const cplx<R>* img, double* partials, int nparts,
                           double* loss, cplx<R>* grad, hipStream_t st);
 template <typename R>
+hipError_t launch_rma_front(const Geo& g, const Tab<R>& t, int logj, const cplx<R>* echoes, double xc, int stype,
+                            void* out, hipStream_t st);  // tffr_rma.hip
+template <typename R>
+hipError_t launch_stolt_rows(const Geo& g, const Tab<R>& t, int stype, const void* samples, const R* phase,
+                             const R* dalong, int part, cplx<R>* out, hipStream_t st);
+template <typename R>
 hipError_t launch_fft(int log2n, int batch, int sign, int max_radix, const cplx<R>* in, cplx<R>* out,
                       const cplx<R>* tw, hipStream_t st);
 

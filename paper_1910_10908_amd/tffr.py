@@ -149,6 +149,32 @@ class Plan:
                                          _ptr(out), _ptr(self.work), _stream()), "tffr_forward")
         return out
 
+    def tffr_rma_front_end(self, echoes, du, xc, out=None):
+        """Raw echoes [n_positions][n_freq] (complex compute type) -> samples of this plan."""
+        J = int(echoes.shape[0]) if echoes.dim() >= 1 else 0
+        ct = torch.complex128 if self.params.dtype == C128 else torch.complex64
+        self._chk(echoes, (J, self.params.n_freq), ct, "echoes")
+        if out is None:
+            if self.params.dtype == C64_FP16IN:
+                out = torch.empty(self.shape_samples + (2,), dtype=torch.float16, device=self.device)
+            else:
+                out = torch.empty(self.shape_samples, dtype=self.ctype, device=self.device)
+        self._chk_samples(out)
+        _lib.check(self.lib.tffr_rma_front_end(self.handle, _ptr(echoes), J, float(du), float(xc), _ptr(out),
+                                               _stream()), "tffr_rma_front_end")
+        return out
+
+    def tffr_stolt_image(self, samples, phase=None, dalong=None, out=None):
+        self._chk_samples(samples)
+        self._chk(phase, (self.params.n_pulses,), self.rtype, "phase")
+        self._chk(dalong, (self.params.n_pulses,), self.rtype, "dalong")
+        if out is None:
+            out = torch.empty(self.shape_image, dtype=self.ctype, device=self.device)
+        self._chk(out, self.shape_image, self.ctype, "image")
+        _lib.check(self.lib.tffr_stolt_image(self.handle, _ptr(samples), _ptr(phase), _ptr(dalong), _ptr(out),
+                                             _ptr(self.work), _stream()), "tffr_stolt_image")
+        return out
+
     def tffr_adjoint(self, grad_image, samples=None, phase=None, dalong=None, user_w=None,
                      want_phase=False, want_dalong=False, out=None):
         self._chk(grad_image, self.shape_image, self.ctype, "grad_image")
