@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-full-swath", action="store_true", help="skip the 4096 x 8192 leg")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="run only this many eager steps of the tFFR path (for profilers) and exit")
+    ap.add_argument("--profile-ffr", action="store_true",
+                    help="with --profile-steps: steps of plain FFR with D re-solved in every step")
     return ap.parse_args()
 
 
@@ -504,8 +506,12 @@ def main():
                                 fov_y=wl.fov, weighting=weighting, kernel_width=w, dtype=T.C64, gridding=gridding,
                                 **kw)
 
-    plan = T.Plan(params(T.W_TFFR), k, ku, dev)
-    step = Step(T, plan, s, ph, da)
+    if args.profile_steps and args.profile_ffr:
+        plan = T.Plan(params(T.W_FFR), k, ku, dev)
+        step = Step(T, plan, s, ph, da, ffr=True)
+    else:
+        plan = T.Plan(params(T.W_TFFR), k, ku, dev)
+        step = Step(T, plan, s, ph, da)
     if args.profile_steps:
         for _ in range(args.profile_steps):
             step()
@@ -517,7 +523,7 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_steps": args.profile_steps, "workload": wl.name,
+        print(json.dumps({"profile_steps": args.profile_steps, "workload": wl.name, "ffr": args.profile_ffr,
                           "copy_bytes": profiling.COPY_BYTES}))
         return
 
