@@ -12,12 +12,12 @@ Readings taken where the paper's matrices do not conform or are under-specified:
   Eq. (4)); q is not given for the frame methods, the default is q = 3.
 * The weight lattice is the image's own DFT lattice: the integers in cycles per field of
   view, infinite and periodic.
-* tFFR keeps only the diagonal of G (Sec. III-C, "isolating the diagonal"):
+* tFFR keeps only the diagonal of G (Sec. III-C isolates it before inverting):
   D = diag(pinv(diag(G))), i.e. 1/g elementwise with 1/0 -> 0, then R_tau.
 * R_tau(x) = x if x >= tau else 0 (Sec. III-B), inclusive, compared on |x| (x is real
   and positive here).  Mode 0 thresholds the entries of the pseudo-inverse as written;
-  mode 1 thresholds the correlation g itself ("preserving only the most correlated
-  values").
+  mode 1 thresholds the correlation g itself (Sec. III-B's interpretation of R_tau as
+  keeping the most strongly correlated frame coefficients).
 * Plain FFR: D = B_r(pinv(G)) with r = 2 (Eq. (8) and Sec. IV, Baselines); B_r keeps
   entries with |p - p'| <= r.
 * Quadrature: trapezoid rule per azimuth slice in lam (Sec. II-B and Sec. IV), half
@@ -35,8 +35,8 @@ THRESH_CORRELATION = 1  # keep iff g >= tau
 def grid_points(lam, q):
     """Integers m with |m - lam| < q, as an array [..., K] plus a validity mask.
 
-    This is the truncation "only lambda_n within a chosen bound q are considered for
-    each l_m" of Eq. (4).
+    This is the truncation of Eq. (4): each grid point l_m takes only the samples within a
+    chosen distance q of it.
     """
     lam = np.asarray(lam, dtype=np.float64)
     kmax = int(np.ceil(q)) + 1

@@ -589,7 +589,7 @@ const char* tffr_status_string(tffr_status s) {
     case TFFR_ERR_NONMONOTONE: return "TFFR_ERR_NONMONOTONE: k is not strictly increasing";
     case TFFR_ERR_LAYOUT: return "TFFR_ERR_LAYOUT: buffer layout or size mismatch";
     case TFFR_ERR_UNSUPPORTED: return "TFFR_ERR_UNSUPPORTED: configuration not supported";
-    case TFFR_ERR_SINGULAR: return "TFFR_ERR_SINGULAR: plain-FFR frame product is singular";
+    case TFFR_ERR_SINGULAR: return "TFFR_ERR_SINGULAR: plain-FFR solve is numerically singular in FP64";
     case TFFR_ERR_NOMEM: return "TFFR_ERR_NOMEM: allocation failed";
     case TFFR_ERR_HIP: return "TFFR_ERR_HIP: HIP runtime error";
     case TFFR_ERR_SCRATCH: return "TFFR_ERR_SCRATCH: the problem needs more than the static scratch array holds";
