@@ -188,8 +188,8 @@ tffr_status tffr_forward(tffr_plan *plan, const void *d_samples, const void *d_p
  *   d_samples   [n_pulses][n_freq] samples in the plan's sample type, written:
  *               s[n][p] = exp(+i kx[n][p] xc) sum_j e[j][p] exp(-i ku_n u_j)
  * xc is the reference range (m) that the matched filter removes.  The plan must come
- * from tffr_plan_create with ku_n = (n - n_pulses/2) 2 pi / (n_positions du) (checked to
- * 1e-9 of the bin width, else TFFR_ERR_ARG); n_positions a power of two, at least 64
+ * from tffr_plan_create with ku_n = (n - floor(n_pulses/2)) 2 pi / (n_positions du)
+ * (checked to 1e-9 of the bin width, else TFFR_ERR_ARG); n_positions a power of two, at least 64
  * and n_pulses (TFFR_ERR_ARG), at most 16384 (8192 for TFFR_C128; else
  * TFFR_ERR_UNSUPPORTED).  No workspace.  Enqueued on `stream`. */
 tffr_status tffr_rma_front_end(tffr_plan *plan, const void *d_echoes, int32_t n_positions, double du,
