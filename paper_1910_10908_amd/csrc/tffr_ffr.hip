@@ -59,9 +59,12 @@ __device__ __forceinline__ void frame_taps(double lam, const Geo& g, int K, doub
 
 // ---------------------------------------------------------------- small dense blocks
 // B x B row-major blocks in the workgroup's scratch (global memory, cache resident); the
-// products keep one row or column of B values in registers.
+// products keep one row or column of B values in registers.  Every block argument of one
+// call is a different block (the reduction never passes a block as both operand and
+// result), which the restrict qualifiers state: the loads of a call need not wait for its
+// stores.
 template <int B>
-__device__ void mm(double* C, const double* X, const double* Y) {  // C = X Y (C distinct from X, Y)
+__device__ void mm(double* __restrict__ C, const double* __restrict__ X, const double* __restrict__ Y) {  // C = X Y
   for (int i = 0; i < B; ++i) {
     double row[B];
 #pragma unroll
@@ -76,7 +79,8 @@ __device__ void mm(double* C, const double* X, const double* Y) {  // C = X Y (C
   }
 }
 template <int B>
-__device__ void mm_acc(double* C, double sgn, const double* X, const double* Y) {  // C += sgn X Y
+__device__ void mm_acc(double* __restrict__ C, double sgn, const double* __restrict__ X,
+                       const double* __restrict__ Y) {  // C += sgn X Y
   for (int i = 0; i < B; ++i) {
     double row[B];
 #pragma unroll
@@ -91,7 +95,7 @@ __device__ void mm_acc(double* C, double sgn, const double* X, const double* Y) 
   }
 }
 template <int B>
-__device__ void left_mul_inplace(const double* X, double* Y) {  // Y = X Y, column by column
+__device__ void left_mul_inplace(const double* __restrict__ X, double* __restrict__ Y) {  // Y = X Y, column by column
   for (int j = 0; j < B; ++j) {
     double col[B];
 #pragma unroll
@@ -105,7 +109,7 @@ __device__ void left_mul_inplace(const double* X, double* Y) {  // Y = X Y, colu
   }
 }
 template <int B>
-__device__ void right_mul_inplace(double* Y, const double* X) {  // Y = Y X, row by row
+__device__ void right_mul_inplace(double* __restrict__ Y, const double* __restrict__ X) {  // Y = Y X, row by row
   for (int i = 0; i < B; ++i) {
     double row[B];
 #pragma unroll
@@ -119,9 +123,65 @@ __device__ void right_mul_inplace(double* Y, const double* X) {  // Y = Y X, row
   }
 }
 // M = M^-1 by Gauss-Jordan elimination with partial pivoting on [M | T] (T: a spare
-// block, left holding the inverse, then copied back); false when a pivot falls below tol.
+// block, left holding the inverse, then copied back; blocks of up to 5 x 5 are eliminated
+// in registers instead); false when a pivot falls below tol.
 template <int B>
-__device__ bool inv_block(double* M, double* T, double tol) {
+__device__ bool inv_block(double* __restrict__ M, double* __restrict__ T, double tol) {
+  if constexpr (B <= 5) {  // small blocks: the whole elimination in registers
+    double a[B][B], t[B][B];
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        a[i][j] = M[i * B + j];
+        t[i][j] = i == j ? 1.0 : 0.0;
+      }
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      int piv = c;
+      double best = fabs(a[c][c]);
+#pragma unroll
+      for (int r = c + 1; r < B; ++r)
+        if (fabs(a[r][c]) > best) {
+          best = fabs(a[r][c]);
+          piv = r;
+        }
+      if (!(best > tol)) return false;
+#pragma unroll
+      for (int r = c + 1; r < B; ++r)
+        if (piv == r)
+#pragma unroll
+          for (int j = 0; j < B; ++j) {
+            double u = a[c][j];
+            a[c][j] = a[r][j];
+            a[r][j] = u;
+            u = t[c][j];
+            t[c][j] = t[r][j];
+            t[r][j] = u;
+          }
+      const double inv = 1.0 / a[c][c];
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        a[c][j] *= inv;
+        t[c][j] *= inv;
+      }
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+        if (r != c) {
+          const double l = a[r][c];
+#pragma unroll
+          for (int j = 0; j < B; ++j) {
+            a[r][j] -= l * a[c][j];
+            t[r][j] -= l * t[c][j];
+          }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < B; ++i)
+#pragma unroll
+      for (int j = 0; j < B; ++j) M[i * B + j] = t[i][j];
+    return true;
+  }
   for (int i = 0; i < B; ++i)
     for (int j = 0; j < B; ++j) T[i * B + j] = i == j ? 1.0 : 0.0;
   for (int c = 0; c < B; ++c) {
