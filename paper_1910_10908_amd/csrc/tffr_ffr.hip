@@ -217,6 +217,108 @@ __device__ bool inv_block(double* __restrict__ M, double* __restrict__ T, double
   return true;
 }
 
+// Register-held B x B blocks (small B): a task loads every operand block it needs at once,
+// computes, and stores its results, one memory round trip instead of one per product.
+template <int B>
+struct Blk {
+  double v[B][B];
+};
+template <int B>
+__device__ __forceinline__ Blk<B> ldb(const double* p) {
+  Blk<B> b;
+#pragma unroll
+  for (int i = 0; i < B; ++i)
+#pragma unroll
+    for (int j = 0; j < B; ++j) b.v[i][j] = p[i * B + j];
+  return b;
+}
+template <int B>
+__device__ __forceinline__ void stb(double* p, const Blk<B>& b, double sgn = 1.0) {
+#pragma unroll
+  for (int i = 0; i < B; ++i)
+#pragma unroll
+    for (int j = 0; j < B; ++j) p[i * B + j] = sgn * b.v[i][j];
+}
+template <int B>
+__device__ __forceinline__ Blk<B> zerob() {
+  Blk<B> b;
+#pragma unroll
+  for (int i = 0; i < B; ++i)
+#pragma unroll
+    for (int j = 0; j < B; ++j) b.v[i][j] = 0.0;
+  return b;
+}
+template <int B>
+__device__ __forceinline__ void macb(Blk<B>& c, double sgn, const Blk<B>& x, const Blk<B>& y) {  // c += sgn x y
+#pragma unroll
+  for (int i = 0; i < B; ++i)
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < B; ++k) acc += x.v[i][k] * y.v[k][j];
+      c.v[i][j] += sgn * acc;
+    }
+}
+template <int B>
+__device__ __forceinline__ Blk<B> mulb(const Blk<B>& x, const Blk<B>& y) {
+  Blk<B> c = zerob<B>();
+  macb<B>(c, 1.0, x, y);
+  return c;
+}
+// a = a^-1 by Gauss-Jordan with partial pivoting; false when a pivot falls below tol
+template <int B>
+__device__ __forceinline__ bool invb(Blk<B>& a, double tol) {
+  Blk<B> t;
+#pragma unroll
+  for (int i = 0; i < B; ++i)
+#pragma unroll
+    for (int j = 0; j < B; ++j) t.v[i][j] = i == j ? 1.0 : 0.0;
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < B; ++c) {
+    int piv = c;
+    double best = fabs(a.v[c][c]);
+#pragma unroll
+    for (int r = c + 1; r < B; ++r)
+      if (fabs(a.v[r][c]) > best) {
+        best = fabs(a.v[r][c]);
+        piv = r;
+      }
+    if (!(best > tol)) ok = false;
+#pragma unroll
+    for (int r = c + 1; r < B; ++r)
+      if (piv == r)
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+          double u = a.v[c][j];
+          a.v[c][j] = a.v[r][j];
+          a.v[r][j] = u;
+          u = t.v[c][j];
+          t.v[c][j] = t.v[r][j];
+          t.v[r][j] = u;
+        }
+    const double inv = ok ? 1.0 / a.v[c][c] : 0.0;
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      a.v[c][j] *= inv;
+      t.v[c][j] *= inv;
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+      if (r != c) {
+        const double l = a.v[r][c];
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+          a.v[r][j] -= l * a.v[c][j];
+          t.v[r][j] -= l * t.v[c][j];
+        }
+      }
+  }
+  a = t;
+  return ok;
+}
+
 // Selected inversion of one banded n x n matrix (half-band <= HB) by block cyclic
 // reduction, by the NT threads of a workgroup.  band [n][2HB+1] (entry (i, j) at
 // i (2HB+1) + HB + j - i) in; zband the same layout out (every entry within the band);
@@ -253,114 +355,249 @@ __device__ bool band_selinv(int n, const double* band, double* work, double* zba
   __syncthreads();
   int top = 1;
   while (top < nb) top *= 2;
-  // ---- elimination, level by level
-  for (int s = 1; s < nb; s *= 2) {
-    // phase 1: eliminated nodes i (odd multiples of s): D_i^-1, X_a = D_i^-1 A_ia,
-    // X_b = D_i^-1 A_ib, and the neighbours' couplings to i
-    for (int k = threadIdx.x;; k += NT) {
-      const int i = s * (2 * k + 1);
-      if (i >= nb) break;
-      const int a = i - s, b = i + s;
-      double* Di = Dm + (size_t)i * BB;
-      if (!inv_block<HB>(Di, Zd + (size_t)i * BB, tol)) bad = 1;
-      left_mul_inplace<HB>(Di, Lm + (size_t)i * BB);  // X_a
-      left_mul_inplace<HB>(Di, Um + (size_t)i * BB);  // X_b (zero when i has no right neighbour)
-      for (int e = 0; e < BB; ++e) Ra[(size_t)i * BB + e] = Um[(size_t)a * BB + e];
-      for (int e = 0; e < BB; ++e) Rb[(size_t)i * BB + e] = b < nb ? Lm[(size_t)b * BB + e] : 0.0;
-    }
-    __syncthreads();
-    // phase 2: surviving nodes j (multiples of 2s) take the Schur complement of both
-    // eliminated neighbours and their new couplings at distance 2s
-    for (int k = threadIdx.x;; k += NT) {
-      const int j = 2 * s * k;
-      if (j >= nb) break;
-      const int il = j - s, ir = j + s;
-      double* Dj = Dm + (size_t)j * BB;
-      if (il >= 0) mm_acc<HB>(Dj, -1.0, Rb + (size_t)il * BB, Um + (size_t)il * BB);  // A_{j,il} X_b(il)
-      if (ir < nb) mm_acc<HB>(Dj, -1.0, Ra + (size_t)ir * BB, Lm + (size_t)ir * BB);  // A_{j,ir} X_a(ir)
-      double* Lj = Lm + (size_t)j * BB;
-      double* Uj = Um + (size_t)j * BB;
-      if (il >= 0) {  // A'_{j, j-2s} = -A_{j,il} X_a(il)
-        mm<HB>(Lj, Rb + (size_t)il * BB, Lm + (size_t)il * BB);
-        for (int e = 0; e < BB; ++e) Lj[e] = -Lj[e];
-      } else {
-        for (int e = 0; e < BB; ++e) Lj[e] = 0.0;
-      }
-      if (ir < nb) {  // A'_{j, j+2s} = -A_{j,ir} X_b(ir)
-        mm<HB>(Uj, Ra + (size_t)ir * BB, Um + (size_t)ir * BB);
-        for (int e = 0; e < BB; ++e) Uj[e] = -Uj[e];
-      } else {
-        for (int e = 0; e < BB; ++e) Uj[e] = 0.0;
-      }
-    }
-    __syncthreads();
-  }
-  // ---- the root (node 0): its Schur complement inverted
-  if (threadIdx.x == 0) {
-    if (!inv_block<HB>(Dm, ZL, tol)) bad = 1;
-    for (int e = 0; e < BB; ++e) Zd[e] = Dm[e];
-  }
-  __syncthreads();
-  // ---- selected inversion back up the levels
-  for (int s = top / 2; s >= 1; s /= 2) {
-    for (int k = threadIdx.x;; k += NT) {
-      const int i = s * (2 * k + 1);
-      if (i >= nb) break;
-      const int a = i - s, b = i + s;
-      const bool hb = b < nb;
-      const double* Xa = Lm + (size_t)i * BB;
-      const double* Xb = Um + (size_t)i * BB;
-      const double* Di = Dm + (size_t)i * BB;
-      const double* Zaa = Zd + (size_t)a * BB;
-      const double* Zbb = Zd + (size_t)(hb ? b : a) * BB;
-      // Z_ab, Z_ba: a and b are neighbours at level 2s; the odd multiple of 2s among them
-      // was eliminated there and holds the pair
-      const double* Zab = nullptr;
-      const double* Zba = nullptr;
-      if (hb) {
-        if ((a / (2 * s)) & 1) {
-          Zab = ZR + (size_t)a * BB;
-          Zba = ZRt + (size_t)a * BB;
-        } else {
-          Zab = ZLt + (size_t)b * BB;
-          Zba = ZL + (size_t)b * BB;
+  if constexpr (HB <= 5) {
+    // Small blocks: every task holds its operand blocks in registers (one batch of loads,
+    // the products, one batch of stores); the independent products of a node are tasks
+    // q = 0..3 of it, on threads 4k + q.
+    using BK = Blk<HB>;
+    for (int s = 1; s < nb; s *= 2) {
+      // eliminated nodes i (odd multiples of s): D_i^-1, X_a = D_i^-1 A_ia, X_b = D_i^-1 A_ib
+      // (task 0), and the neighbours' couplings to i (task 1)
+      for (int w = threadIdx.x;; w += NT) {
+        const int k = w >> 2, q = w & 3;
+        const int i = s * (2 * k + 1);
+        if (i >= nb) break;
+        const int a = i - s, b = i + s;
+        if (q == 0) {
+          BK d = ldb<HB>(Dm + (size_t)i * BB);
+          const BK l = ldb<HB>(Lm + (size_t)i * BB), u = ldb<HB>(Um + (size_t)i * BB);
+          if (!invb<HB>(d, tol)) bad = 1;
+          stb<HB>(Dm + (size_t)i * BB, d);
+          stb<HB>(Lm + (size_t)i * BB, mulb<HB>(d, l));
+          stb<HB>(Um + (size_t)i * BB, mulb<HB>(d, u));
+        } else if (q == 1) {
+          const BK ra = ldb<HB>(Um + (size_t)a * BB);
+          const BK rb = b < nb ? ldb<HB>(Lm + (size_t)b * BB) : zerob<HB>();
+          stb<HB>(Ra + (size_t)i * BB, ra);
+          stb<HB>(Rb + (size_t)i * BB, rb);
         }
       }
-      double* zl = ZL + (size_t)i * BB;
-      double* zr = ZR + (size_t)i * BB;
-      double* zlt = ZLt + (size_t)i * BB;
-      double* zrt = ZRt + (size_t)i * BB;
-      // Z_{i,a} = -(X_a Z_aa + X_b Z_ba), Z_{i,b} = -(X_a Z_ab + X_b Z_bb)
-      mm<HB>(zl, Xa, Zaa);
-      if (hb) mm_acc<HB>(zl, 1.0, Xb, Zba);
-      for (int e = 0; e < BB; ++e) zl[e] = -zl[e];
-      if (hb) {
-        mm<HB>(zr, Xa, Zab);
-        mm_acc<HB>(zr, 1.0, Xb, Zbb);
-        for (int e = 0; e < BB; ++e) zr[e] = -zr[e];
-      } else {
-        for (int e = 0; e < BB; ++e) zr[e] = 0.0;
+      __syncthreads();
+      // surviving nodes j (multiples of 2s): Schur complement of both eliminated neighbours
+      // (task 0), new couplings at distance 2s (tasks 1 and 2)
+      for (int w = threadIdx.x;; w += NT) {
+        const int k = w >> 2, q = w & 3;
+        const int j = 2 * s * k;
+        if (j >= nb) break;
+        const int il = j - s, ir = j + s;
+        if (q == 0) {
+          BK d = ldb<HB>(Dm + (size_t)j * BB);
+          const BK rbl = il >= 0 ? ldb<HB>(Rb + (size_t)il * BB) : zerob<HB>();
+          const BK xbl = il >= 0 ? ldb<HB>(Um + (size_t)il * BB) : zerob<HB>();
+          const BK rar = ir < nb ? ldb<HB>(Ra + (size_t)ir * BB) : zerob<HB>();
+          const BK xar = ir < nb ? ldb<HB>(Lm + (size_t)ir * BB) : zerob<HB>();
+          macb<HB>(d, -1.0, rbl, xbl);  // A_{j,il} X_b(il)
+          macb<HB>(d, -1.0, rar, xar);  // A_{j,ir} X_a(ir)
+          stb<HB>(Dm + (size_t)j * BB, d);
+        } else if (q == 1) {  // A'_{j, j-2s} = -A_{j,il} X_a(il)
+          const BK lj = il >= 0 ? mulb<HB>(ldb<HB>(Rb + (size_t)il * BB), ldb<HB>(Lm + (size_t)il * BB)) : zerob<HB>();
+          stb<HB>(Lm + (size_t)j * BB, lj, -1.0);
+        } else if (q == 2) {  // A'_{j, j+2s} = -A_{j,ir} X_b(ir)
+          const BK uj = ir < nb ? mulb<HB>(ldb<HB>(Ra + (size_t)ir * BB), ldb<HB>(Um + (size_t)ir * BB)) : zerob<HB>();
+          stb<HB>(Um + (size_t)j * BB, uj, -1.0);
+        }
       }
-      // Z_{a,i} = -(Z_aa A_{a,i} + Z_ab A_{b,i}) D_i^-1, Z_{b,i} = -(Z_ba A_{a,i} + Z_bb A_{b,i}) D_i^-1
-      mm<HB>(zlt, Zaa, Ra + (size_t)i * BB);
-      if (hb) mm_acc<HB>(zlt, 1.0, Zab, Rb + (size_t)i * BB);
-      right_mul_inplace<HB>(zlt, Di);
-      for (int e = 0; e < BB; ++e) zlt[e] = -zlt[e];
-      if (hb) {
-        mm<HB>(zrt, Zba, Ra + (size_t)i * BB);
-        mm_acc<HB>(zrt, 1.0, Zbb, Rb + (size_t)i * BB);
-        right_mul_inplace<HB>(zrt, Di);
-        for (int e = 0; e < BB; ++e) zrt[e] = -zrt[e];
-      } else {
-        for (int e = 0; e < BB; ++e) zrt[e] = 0.0;
-      }
-      // Z_ii = D_i^-1 - X_a Z_{a,i} - X_b Z_{b,i}
-      double* Zi = Zd + (size_t)i * BB;
-      for (int e = 0; e < BB; ++e) Zi[e] = Di[e];
-      mm_acc<HB>(Zi, -1.0, Xa, zlt);
-      if (hb) mm_acc<HB>(Zi, -1.0, Xb, zrt);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {  // the root (node 0): its Schur complement inverted
+      BK d = ldb<HB>(Dm);
+      if (!invb<HB>(d, tol)) bad = 1;
+      stb<HB>(Dm, d);
+      stb<HB>(Zd, d);
     }
     __syncthreads();
+    for (int s = top / 2; s >= 1; s /= 2) {
+      // the four couplings of Z of each node eliminated at level s
+      for (int w = threadIdx.x;; w += NT) {
+        const int k = w >> 2, q = w & 3;
+        const int i = s * (2 * k + 1);
+        if (i >= nb) break;
+        const int a = i - s, b = i + s;
+        const bool hb = b < nb;
+        const double* pab = nullptr;
+        const double* pba = nullptr;
+        if (hb) {
+          if ((a / (2 * s)) & 1) {
+            pab = ZR + (size_t)a * BB;
+            pba = ZRt + (size_t)a * BB;
+          } else {
+            pab = ZLt + (size_t)b * BB;
+            pba = ZL + (size_t)b * BB;
+          }
+        }
+        if (q == 0) {  // Z_{i,a} = -(X_a Z_aa + X_b Z_ba)
+          const BK xa = ldb<HB>(Lm + (size_t)i * BB), zaa = ldb<HB>(Zd + (size_t)a * BB);
+          const BK xb = hb ? ldb<HB>(Um + (size_t)i * BB) : zerob<HB>();
+          const BK zba = hb ? ldb<HB>(pba) : zerob<HB>();
+          BK z = mulb<HB>(xa, zaa);
+          macb<HB>(z, 1.0, xb, zba);
+          stb<HB>(ZL + (size_t)i * BB, z, -1.0);
+        } else if (q == 1) {  // Z_{i,b} = -(X_a Z_ab + X_b Z_bb)
+          BK z = zerob<HB>();
+          if (hb) {
+            const BK xa = ldb<HB>(Lm + (size_t)i * BB), zab = ldb<HB>(pab);
+            const BK xb = ldb<HB>(Um + (size_t)i * BB), zbb = ldb<HB>(Zd + (size_t)b * BB);
+            z = mulb<HB>(xa, zab);
+            macb<HB>(z, 1.0, xb, zbb);
+          }
+          stb<HB>(ZR + (size_t)i * BB, z, -1.0);
+        } else if (q == 2) {  // Z_{a,i} = -(Z_aa A_{a,i} + Z_ab A_{b,i}) D_i^-1
+          const BK zaa = ldb<HB>(Zd + (size_t)a * BB), ra = ldb<HB>(Ra + (size_t)i * BB);
+          const BK zab = hb ? ldb<HB>(pab) : zerob<HB>();
+          const BK rb = hb ? ldb<HB>(Rb + (size_t)i * BB) : zerob<HB>();
+          const BK di = ldb<HB>(Dm + (size_t)i * BB);
+          BK z = mulb<HB>(zaa, ra);
+          macb<HB>(z, 1.0, zab, rb);
+          stb<HB>(ZLt + (size_t)i * BB, mulb<HB>(z, di), -1.0);
+        } else {  // Z_{b,i} = -(Z_ba A_{a,i} + Z_bb A_{b,i}) D_i^-1
+          BK z = zerob<HB>();
+          if (hb) {
+            const BK zba = ldb<HB>(pba), ra = ldb<HB>(Ra + (size_t)i * BB);
+            const BK zbb = ldb<HB>(Zd + (size_t)b * BB), rb = ldb<HB>(Rb + (size_t)i * BB);
+            const BK di = ldb<HB>(Dm + (size_t)i * BB);
+            BK y = mulb<HB>(zba, ra);
+            macb<HB>(y, 1.0, zbb, rb);
+            z = mulb<HB>(y, di);
+          }
+          stb<HB>(ZRt + (size_t)i * BB, z, -1.0);
+        }
+      }
+      __syncthreads();
+      // Z_ii = D_i^-1 - X_a Z_{a,i} - X_b Z_{b,i}
+      for (int k = threadIdx.x;; k += NT) {
+        const int i = s * (2 * k + 1);
+        if (i >= nb) break;
+        const bool hb = i + s < nb;
+        BK z = ldb<HB>(Dm + (size_t)i * BB);
+        const BK xa = ldb<HB>(Lm + (size_t)i * BB), zlt = ldb<HB>(ZLt + (size_t)i * BB);
+        const BK xb = hb ? ldb<HB>(Um + (size_t)i * BB) : zerob<HB>();
+        const BK zrt = hb ? ldb<HB>(ZRt + (size_t)i * BB) : zerob<HB>();
+        macb<HB>(z, -1.0, xa, zlt);
+        macb<HB>(z, -1.0, xb, zrt);
+        stb<HB>(Zd + (size_t)i * BB, z);
+      }
+      __syncthreads();
+    }
+  } else {
+    // ---- elimination, level by level
+    for (int s = 1; s < nb; s *= 2) {
+      // phase 1: eliminated nodes i (odd multiples of s): D_i^-1, X_a = D_i^-1 A_ia,
+      // X_b = D_i^-1 A_ib, and the neighbours' couplings to i
+      for (int k = threadIdx.x;; k += NT) {
+        const int i = s * (2 * k + 1);
+        if (i >= nb) break;
+        const int a = i - s, b = i + s;
+        double* Di = Dm + (size_t)i * BB;
+        if (!inv_block<HB>(Di, Zd + (size_t)i * BB, tol)) bad = 1;
+        left_mul_inplace<HB>(Di, Lm + (size_t)i * BB);  // X_a
+        left_mul_inplace<HB>(Di, Um + (size_t)i * BB);  // X_b (zero when i has no right neighbour)
+        for (int e = 0; e < BB; ++e) Ra[(size_t)i * BB + e] = Um[(size_t)a * BB + e];
+        for (int e = 0; e < BB; ++e) Rb[(size_t)i * BB + e] = b < nb ? Lm[(size_t)b * BB + e] : 0.0;
+      }
+      __syncthreads();
+      // phase 2: surviving nodes j (multiples of 2s) take the Schur complement of both
+      // eliminated neighbours and their new couplings at distance 2s
+      for (int k = threadIdx.x;; k += NT) {
+        const int j = 2 * s * k;
+        if (j >= nb) break;
+        const int il = j - s, ir = j + s;
+        double* Dj = Dm + (size_t)j * BB;
+        if (il >= 0) mm_acc<HB>(Dj, -1.0, Rb + (size_t)il * BB, Um + (size_t)il * BB);  // A_{j,il} X_b(il)
+        if (ir < nb) mm_acc<HB>(Dj, -1.0, Ra + (size_t)ir * BB, Lm + (size_t)ir * BB);  // A_{j,ir} X_a(ir)
+        double* Lj = Lm + (size_t)j * BB;
+        double* Uj = Um + (size_t)j * BB;
+        if (il >= 0) {  // A'_{j, j-2s} = -A_{j,il} X_a(il)
+          mm<HB>(Lj, Rb + (size_t)il * BB, Lm + (size_t)il * BB);
+          for (int e = 0; e < BB; ++e) Lj[e] = -Lj[e];
+        } else {
+          for (int e = 0; e < BB; ++e) Lj[e] = 0.0;
+        }
+        if (ir < nb) {  // A'_{j, j+2s} = -A_{j,ir} X_b(ir)
+          mm<HB>(Uj, Ra + (size_t)ir * BB, Um + (size_t)ir * BB);
+          for (int e = 0; e < BB; ++e) Uj[e] = -Uj[e];
+        } else {
+          for (int e = 0; e < BB; ++e) Uj[e] = 0.0;
+        }
+      }
+      __syncthreads();
+    }
+    // ---- the root (node 0): its Schur complement inverted
+    if (threadIdx.x == 0) {
+      if (!inv_block<HB>(Dm, ZL, tol)) bad = 1;
+      for (int e = 0; e < BB; ++e) Zd[e] = Dm[e];
+    }
+    __syncthreads();
+    // ---- selected inversion back up the levels
+    for (int s = top / 2; s >= 1; s /= 2) {
+      for (int k = threadIdx.x;; k += NT) {
+        const int i = s * (2 * k + 1);
+        if (i >= nb) break;
+        const int a = i - s, b = i + s;
+        const bool hb = b < nb;
+        const double* Xa = Lm + (size_t)i * BB;
+        const double* Xb = Um + (size_t)i * BB;
+        const double* Di = Dm + (size_t)i * BB;
+        const double* Zaa = Zd + (size_t)a * BB;
+        const double* Zbb = Zd + (size_t)(hb ? b : a) * BB;
+        // Z_ab, Z_ba: a and b are neighbours at level 2s; the odd multiple of 2s among them
+        // was eliminated there and holds the pair
+        const double* Zab = nullptr;
+        const double* Zba = nullptr;
+        if (hb) {
+          if ((a / (2 * s)) & 1) {
+            Zab = ZR + (size_t)a * BB;
+            Zba = ZRt + (size_t)a * BB;
+          } else {
+            Zab = ZLt + (size_t)b * BB;
+            Zba = ZL + (size_t)b * BB;
+          }
+        }
+        double* zl = ZL + (size_t)i * BB;
+        double* zr = ZR + (size_t)i * BB;
+        double* zlt = ZLt + (size_t)i * BB;
+        double* zrt = ZRt + (size_t)i * BB;
+        // Z_{i,a} = -(X_a Z_aa + X_b Z_ba), Z_{i,b} = -(X_a Z_ab + X_b Z_bb)
+        mm<HB>(zl, Xa, Zaa);
+        if (hb) mm_acc<HB>(zl, 1.0, Xb, Zba);
+        for (int e = 0; e < BB; ++e) zl[e] = -zl[e];
+        if (hb) {
+          mm<HB>(zr, Xa, Zab);
+          mm_acc<HB>(zr, 1.0, Xb, Zbb);
+          for (int e = 0; e < BB; ++e) zr[e] = -zr[e];
+        } else {
+          for (int e = 0; e < BB; ++e) zr[e] = 0.0;
+        }
+        // Z_{a,i} = -(Z_aa A_{a,i} + Z_ab A_{b,i}) D_i^-1, Z_{b,i} = -(Z_ba A_{a,i} + Z_bb A_{b,i}) D_i^-1
+        mm<HB>(zlt, Zaa, Ra + (size_t)i * BB);
+        if (hb) mm_acc<HB>(zlt, 1.0, Zab, Rb + (size_t)i * BB);
+        right_mul_inplace<HB>(zlt, Di);
+        for (int e = 0; e < BB; ++e) zlt[e] = -zlt[e];
+        if (hb) {
+          mm<HB>(zrt, Zba, Ra + (size_t)i * BB);
+          mm_acc<HB>(zrt, 1.0, Zbb, Rb + (size_t)i * BB);
+          right_mul_inplace<HB>(zrt, Di);
+          for (int e = 0; e < BB; ++e) zrt[e] = -zrt[e];
+        } else {
+          for (int e = 0; e < BB; ++e) zrt[e] = 0.0;
+        }
+        // Z_ii = D_i^-1 - X_a Z_{a,i} - X_b Z_{b,i}
+        double* Zi = Zd + (size_t)i * BB;
+        for (int e = 0; e < BB; ++e) Zi[e] = Di[e];
+        mm_acc<HB>(Zi, -1.0, Xa, zlt);
+        if (hb) mm_acc<HB>(Zi, -1.0, Xb, zrt);
+      }
+      __syncthreads();
+    }
   }
   // ---- scalar band of the inverse
   for (int idx = threadIdx.x; idx < n * WD; idx += NT) {
