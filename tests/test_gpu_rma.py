@@ -176,3 +176,20 @@ def test_raw_echoes_to_images_focus_on_the_scatterers():
     prob = OP.Problem(k=k, ku=ku, mx=mx, my=my, fov_x=fov_x, fov_y=fov_y)
     ref = ORMA.stolt_image(prob, sref)
     assert rel_l2(plan.tffr_stolt_image(s).cpu().numpy(), ref) < 1e-5
+
+
+def test_front_end_largest_transform():
+    """J = 16384 raw positions (the longest azimuth transform, one fast-time column per
+    workgroup filling 128 KB of LDS): against the oracle on every column."""
+    n_pulses, n_freq = 8192, 24
+    k, ku = scenes.radar_sampling(n_pulses, n_freq)
+    J, du = scenes.rma_positions(n_pulses)
+    assert J == 16384
+    prm = T.default_params(n_pulses=n_pulses, n_freq=n_freq, mx=64, my=64, fov_x=40.0, fov_y=40.0)
+    plan = T.Plan(prm, k, ku, DEV)
+    e = _echoes(J, n_freq, 29)
+    got = plan.tffr_rma_front_end(torch.as_tensor(e, dtype=torch.complex64, device=DEV), du, 900.0).cpu().numpy()
+    ref, _ = ORMA.front_end(e.astype(np.complex64).astype(np.complex128), k, du, 900.0, n_pulses)
+    err = _max_rel(got, ref)
+    print(f"  J = 16384: max-rel {err:.2e}", flush=True)
+    assert err < 5e-6
