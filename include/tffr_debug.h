@@ -34,8 +34,9 @@ tffr_status tffr_debug_rows(tffr_plan *plan, int32_t stage, const void *d_sample
  * tffr_forward. */
 tffr_status tffr_debug_cols(tffr_plan *plan, const void *d_hx, void *d_image, tffr_stream stream);
 
-/* Launch configuration the plan chose: range_mode 0 (sub-pass gridding) or 1
- * (sliding-window runs, dense slices); az_cols range columns per azimuth workgroup;
+/* Launch configuration the plan chose: range_mode 0 (sub-pass gridding: kernels wider
+ * than 8 cells, literal lattice taps) or 1 (runs of read-add-writes: every other plan);
+ * az_cols range columns per azimuth workgroup;
  * ent_fused 1 when tffr_entropy_step uses the fused azimuth kernel.  Any pointer may be
  * NULL. */
 tffr_status tffr_debug_plan_config(const tffr_plan *plan, int32_t *range_mode, int32_t *az_cols,

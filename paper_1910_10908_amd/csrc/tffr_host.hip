@@ -508,31 +508,26 @@ hipError_t record_mark(void* ctx, int i) {
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
-// Range gridding schedule (see k_fwd_rows): S = samples a thread owns so that samples S
-// apart are more than W fine cells apart, and the part length so that no part of a
-// slice spans the fine row (after wrapping, two samples of a part never share cells).
-// Range gridding schedule.  U = kx fov_x nfx / (2 pi mx) is a sample's unwrapped fine
-// cell coordinate.  S (samples per thread run / per sub-pass group) satisfies
+// Range gridding schedule (see k_fwd_rows, k_fwd_rows_run).  U = kx fov_x nfx / (2 pi mx)
+// is a sample's unwrapped fine cell coordinate.  S (samples per thread run / per sub-pass group) satisfies
 // S * (smallest spacing of U) > W + 1, one cell of margin over the W-cell tap span, so
 // the taps of samples S apart never meet even when a fraction rounds across a cell
-// boundary.  Slices are cut into parts whose span (plus taps) stays inside the fine row.
-// The sliding-window kernel (mode 1) serves dense slices, where consecutive samples are
-// under kDenseSpacing cells apart; each of its threads takes at most one run per part.
-constexpr double kDenseSpacing = 2.5;
+// boundary.  Slices are cut into parts whose span (plus taps) stays inside the fine row, so
+// after wrapping two samples of a part never share cells.  The run kernel (mode 1) serves
+// every plan with W <= kRunWindow and kernel gridding, dense or sparse; each of its
+// threads takes at most one run per part.  The sub-pass kernel (mode 0) serves wider
+// kernels and the literal lattice taps.
 
 void range_schedule(const tffr_params* p, const HostKx& kx, int nfx, int W, int nt, int* S, int* part_len,
                     int* mode) {
   const double tx = p->fov_x / (2.0 * kPi * p->mx);
   const int P = p->n_freq;
-  double smin = 1e300, smax = 0.0;
+  double smin = 1e300;
   int Q = 1;
   std::vector<double> U(P);
   for (int n = 0; n < p->n_pulses; ++n) {
     for (int i = 0; i < P; ++i) U[i] = kx(n, i) * tx * nfx;
-    for (int i = 0; i + 1 < P; ++i) {
-      smin = std::min(smin, U[i + 1] - U[i]);
-      smax = std::max(smax, U[i + 1] - U[i]);
-    }
+    for (int i = 0; i + 1 < P; ++i) smin = std::min(smin, U[i + 1] - U[i]);
     for (;; ++Q) {
       const int len = (P + Q - 1) / Q;
       bool ok = true;
@@ -549,7 +544,7 @@ void range_schedule(const tffr_params* p, const HostKx& kx, int nfx, int W, int 
     s = (int)std::min<double>((double)P, std::floor((W + 1.0) / sm) + 1.0);
   }
   *S = std::max(1, s);
-  int m = (P > 1 && W <= tffr::kRunWindow && smax < kDenseSpacing) ? 1 : 0;
+  int m = (P > 1 && W <= tffr::kRunWindow) ? 1 : 0;
   if (p->gridding == TFFR_GRID_LITERAL) m = 0;  // lattice taps: sub-pass kernel only
   else if (const char* e = std::getenv("TFFR_RANGE_MODE")) {
     const int v = std::atoi(e);

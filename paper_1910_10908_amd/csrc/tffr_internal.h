@@ -28,7 +28,7 @@ struct Geo {
   int32_t use_poly, nseg, deg;  // tFFR weight polynomial (float path)
   int32_t sub;                  // range gridding: samples per thread per sub-pass group
   int32_t part_len;             // range gridding: samples per part (part span < fine row)
-  int32_t range_mode;           // range gridding: 0 sub-passes, 1 sliding-window runs (dense slices)
+  int32_t range_mode;           // range gridding: 0 sub-passes, 1 runs of read-add-writes (W <= kRunWindow)
   int32_t yemax;                // azimuth gridding: most (slice, tap) pairs reaching one cell
   int32_t keep0;                // threshold decision for a sample exactly on the lattice
   double beta;                  // ES kernel shape
@@ -136,6 +136,7 @@ size_t max_dynamic_lds();  // bytes of LDS one workgroup may use on this device
 int rows_threads(int logn);  // threads per workgroup of the range-stage kernels for a 2^logn fine row
 constexpr int kPolySeg = 32;  // segments of the tFFR weight polynomial on (0, 1)
 constexpr int kPolyDeg = 7;   // degree per segment
-constexpr int kRunWindow = 8;  // register window of the sliding-window range kernel (widths up to 8)
+constexpr int kRunWindow = 8;    // widest kernel of the run range kernel (its pad and halos are 2 kRunWindow cells)
+constexpr int kRunHaloInts = 16;  // LDS ints for the run kernel's per-wave halo start cells (up to 16 waves)
 
 }  // namespace tffr

@@ -1,5 +1,5 @@
 // Range-stage kernels of libtffr: type-1 gridding of each azimuth slice with the fused
-// coordinate prep and weights (sub-pass and sliding-window variants), and the type-2
+// coordinate prep and weights (sub-pass and run variants), and the type-2
 // range adjoint with the per-slice phase / position gradient reduction.
 
 #include "tffr_device.h"
@@ -112,16 +112,28 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(Geo g, Tab<R> t, int stype, con
   }
 }
 
-// Range stage for densely sampled slices (the plan's choice when consecutive samples sit
-// well under W fine cells apart).  Thread t takes the run of S consecutive samples
-// p0 = part start + S t ... and slides a window of W register accumulators along the
-// fine row: a sample whose first tap cell is c0 first retires the window cells below c0
-// (in increasing cell order), then adds its W taps to the window at fixed register
-// positions.  With S * (smallest sample spacing) > W, the first W cells a run retires
-// (its "lead") are the only cells another run (the previous one) also reaches, so
-// every other retired cell is read-add-written into LDS at once without conflict; the
-// lead cells are kept in registers and added after one barrier, when no other run
-// writes.  Two barriers per part instead of one per sample of a run.
+// Range stage, run variant (the plan's choice for non-literal gridding with W <= WM).
+// Thread t takes the run of S consecutive samples p0 = part start + S t ... and
+// read-add-writes each sample's W taps straight into the LDS row.  The lanes of a wave
+// step through their runs together, and samples S apart are more than W cells apart
+// (the plan picks S with S * (smallest sample spacing) > W + 1), so no two lanes touch a
+// cell in the same step; a wave's LDS operations complete in issue order, so a cell two
+// lanes reach in different steps is updated in turn.  Runs only meet their neighbours'
+// cells, and only the first run of each wave (lane 0) has its neighbour in another wave:
+// that lane sends the taps of its samples that start within W cells of its run's first
+// cell to a halo of its own, added to the row after the part's barrier.  Taps that run
+// past the row end land in a pad of PAD cells, folded onto the row start before the FFT.
+// The WW taps of one sample read-add-written at dst[0, WW): the cells are read back to
+// back, the kernel values formed meanwhile, then the sums written.
+template <int WW, typename R>
+__device__ __forceinline__ void run_taps(cplx<R>* dst, R z0, R dz, R beta, cplx<R> c) {
+  cplx<R> v[WW];
+#pragma unroll
+  for (int i = 0; i < WW; ++i) v[i] = dst[i];
+#pragma unroll
+  for (int i = 0; i < WW; ++i) dst[i] = v[i] + es_kernel(z0 + (R)i * dz, beta) * c;
+}
+
 template <typename R, int LOGN, int NT, int WM>
 __global__ __launch_bounds__(NT) void k_fwd_rows_run(Geo g, Tab<R> t, int stype, const void* __restrict__ samples,
                                                      const R* __restrict__ phase, const R* __restrict__ dalong,
@@ -129,17 +141,22 @@ __global__ __launch_bounds__(NT) void k_fwd_rows_run(Geo g, Tab<R> t, int stype,
                                                      int stage) {
   constexpr int N = 1 << LOGN;
   constexpr int DPT = (N + NT - 1) / NT;
+  constexpr int NW = NT / 64;
+  constexpr int PAD = 2 * WM;
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
-  cplx<R>* buf = tw + tw_entries<N>();
-  float* lpoly = reinterpret_cast<float*>(buf + N);
+  cplx<R>* buf = tw + tw_entries<N>();  // [N + PAD]
+  cplx<R>* halo = buf + N + PAD;        // [NW][PAD]
+  int* hcf = reinterpret_cast<int*>(halo + NW * PAD);  // [NW] halo's first cell (-1: none)
+  float* lpoly = reinterpret_cast<float*>(hcf + kRunHaloInts);
   const int n = blockIdx.x;
   const bool ffr = g.weighting == 2;
   const int S = g.sub, W = g.W, plen = g.part_len;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const size_t base_s = (size_t)n * g.n_freq;
   load_twiddles<N, NT>(tw, t.twx);
   const float* poly = load_poly<NT>(g, t.poly, lpoly);
-  for (int i = threadIdx.x; i < N; i += NT) buf[i] = {0, 0};
+  for (int i = threadIdx.x; i < N + PAD + NW * PAD; i += NT) buf[i] = {0, 0};
   const cplx<R> rot = row_rotation(t, phase, dalong, n);
   const double ku = t.ku[n];
   const R halfw = (R)(0.5 * g.W), inv_halfw = (R)(2.0 / g.W), beta = es_shape<R>(g);
@@ -148,26 +165,7 @@ __global__ __launch_bounds__(NT) void k_fwd_rows_run(Geo g, Tab<R> t, int stype,
     const int pb = min(pa + plen, g.n_freq);
     const int p0 = pa + S * (int)threadIdx.x;
     const int p1 = min(p0 + S, pb);
-    cplx<R> acc[WM], lead[WM];
-#pragma unroll
-    for (int i = 0; i < WM; ++i) acc[i] = lead[i] = cplx<R>{0, 0};
-    int base = 0, cfirst = 0;
-    // retire the lowest window cell: into the lead registers if it is one of the run's
-    // first W cells, else straight into the row; then shift the window down one cell
-    auto retire = [&]() {
-      if (base - cfirst < W) {
-#pragma unroll
-        for (int i = 0; i + 1 < WM; ++i) lead[i] = lead[i + 1];
-        lead[WM - 1] = acc[0];
-      } else {
-        cplx<R>& bb = buf[base & (N - 1)];
-        bb = bb + acc[0];
-      }
-#pragma unroll
-      for (int i = 0; i + 1 < WM; ++i) acc[i] = acc[i + 1];
-      acc[WM - 1] = cplx<R>{0, 0};
-      ++base;
-    };
+    int cfirst = 0;
     double k_nx = p0 < p1 ? raw_k(t, g.n_freq, n, p0) : 0.0;
     cplx<R> s_nx = (p0 < p1 && !ffr) ? load_sample<R>(samples, stype, base_s + p0) : cplx<R>{0, 0};
     for (int p = p0; p < p1; ++p) {
@@ -188,32 +186,41 @@ __global__ __launch_bounds__(NT) void k_fwd_rows_run(Geo g, Tab<R> t, int stype,
       const int k0 = (int)ceil(f - halfw);
       // unwrapped first tap cell (only differences and the low LOGN bits are used)
       const int c0 = (int)((unsigned)(int)floor(tt) * (unsigned)N + (unsigned)(ui + k0));
-      if (p == p0) base = cfirst = c0;  // the run's lead region starts at its first sample
-      if (!kept) continue;  // removed by the threshold: the next kept sample retires the gap
-      for (int adv = c0 - base; adv > 0; --adv) retire();
+      if (p == p0) cfirst = c0;
+      if (!kept) continue;  // removed by the threshold: no taps
+      const int rel = c0 - cfirst;
+      cplx<R>* dst = (lane == 0 && rel < W) ? halo + wv * PAD + rel : buf + (c0 & (N - 1));
       const R z0 = ((R)k0 - f) * inv_halfw;
-#pragma unroll
-      for (int i = 0; i < WM; ++i) {
-        if (i < W) {
-          const R phi = es_kernel(z0 + (R)i * inv_halfw, beta);
-          acc[i] = acc[i] + phi * c;
-        }
+      switch (W) {  // uniform: one unrolled tap block per kernel width
+#define TFFR_RUN_TAPS(WW) \
+  case WW: run_taps<WW>(dst, z0, inv_halfw, beta, c); break;
+        TFFR_RUN_TAPS(2)
+        TFFR_RUN_TAPS(3)
+        TFFR_RUN_TAPS(4)
+        TFFR_RUN_TAPS(5)
+        TFFR_RUN_TAPS(6)
+        TFFR_RUN_TAPS(7)
+        TFFR_RUN_TAPS(8)
+#undef TFFR_RUN_TAPS
       }
     }
-    if (p0 < p1)
-      for (int i = 0; i < W; ++i) retire();
+    if (lane == 0) hcf[wv] = p0 < p1 ? (cfirst & (N - 1)) : -1;
     __syncthreads();
-    if (p0 < p1) {
-#pragma unroll
-      for (int i = 0; i < WM; ++i) {
-        if (i >= WM - W) {
-          cplx<R>& bb = buf[(cfirst + i - (WM - W)) & (N - 1)];
-          bb = bb + lead[i];
-        }
+    // halos onto the row: distinct waves' halos hold distinct cells of the part
+    for (int i = threadIdx.x; i < NW * PAD; i += NT) {
+      const int hw = i / PAD, j = i - hw * PAD;
+      const int cf = hcf[hw];
+      if (cf >= 0) {
+        cplx<R>& bb = buf[cf + j];
+        bb = bb + halo[i];
       }
+      halo[i] = cplx<R>{0, 0};
     }
     __syncthreads();
   }
+  // the pad onto the row start
+  if (threadIdx.x < PAD) buf[threadIdx.x] = buf[threadIdx.x] + buf[N + threadIdx.x];
+  __syncthreads();
   if (stage == 0) {
     for (int i = threadIdx.x; i < N; i += NT) out[(size_t)n * N + i] = buf[i];
     return;
@@ -390,11 +397,14 @@ int rows_threads(int logn) {
 template <typename R>
 hipError_t launch_fwd_rows(const Geo& g, const Tab<R>& t, int stype, const void* samples, const R* phase,
                            const R* dalong, const R* w, cplx<R>* out, int stage, hipStream_t st) {
-  const size_t lds = sizeof(cplx<R>) * (((size_t)1 << g.lognfx) + ((size_t)1 << g.lognfx) / 64 + 64) +
-                     sizeof(float) * kPolyLds;
+  size_t lds = sizeof(cplx<R>) * (((size_t)1 << g.lognfx) + ((size_t)1 << g.lognfx) / 64 + 64) +
+               sizeof(float) * kPolyLds;
   if (g.range_mode == 1 && g.W > kRunWindow) return hipErrorInvalidValue;
   TFFR_LOGN_DISPATCH(g.lognfx, {
     constexpr int NT = nt_for<L>();
+    static_assert(NT / 64 <= kRunHaloInts, "run kernel halos");
+    // run kernel: the row's pad and one halo per wave, 2 kRunWindow cells each
+    if (g.range_mode == 1) lds += sizeof(cplx<R>) * (size_t)(2 * kRunWindow) * (1 + NT / 64) + sizeof(int) * kRunHaloInts;
     auto fn = g.range_mode == 1
                   ? k_fwd_rows_run<R, L, NT, kRunWindow>
                   : (g.sub <= 4 ? k_fwd_rows<R, L, NT, 4>

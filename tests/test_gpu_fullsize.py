@@ -109,10 +109,11 @@ def test_precision_study_fp32_and_fp16_2k():
 
 
 def test_launch_configuration_by_density():
-    """Sparse slices (512 x 1024: ~3.1-3.6 fine cells apart) take the sub-pass range
-    kernel, dense ones (2048 x 4096, 4096 x 8192: under one cell apart) the sliding-window
-    kernel; every full-size plan runs the fused entropy azimuth kernel."""
-    for name, mode in (("ffr_vs_tffr_c64", 0), ("autofocus_1k", 1), ("precision_2k", 1), ("full_swath_4k", 1)):
+    """Sparse slices (512 x 1024: ~3.1-3.6 fine cells apart) and dense ones (2048 x 4096,
+    4096 x 8192: under one cell apart) all take the run range kernel at width 7; the
+    literal lattice taps take the sub-pass kernel; every full-size plan runs the fused
+    entropy azimuth kernel."""
+    for name, mode in (("ffr_vs_tffr_c64", 1), ("autofocus_1k", 1), ("precision_2k", 1), ("full_swath_4k", 1)):
         wl = scenes.WORKLOADS[name]
         k, ku = scenes.radar_sampling(wl.n_pulses, wl.n_freq)
         prm = T.default_params(n_pulses=wl.n_pulses, n_freq=wl.n_freq, mx=wl.m, my=wl.m, fov_x=wl.fov,
@@ -121,6 +122,11 @@ def test_launch_configuration_by_density():
         print(f"  {name}: range mode {plan.range_mode}, azimuth columns {plan.az_cols}, fused {plan.ent_fused}",
               flush=True)
         assert plan.range_mode == mode and plan.ent_fused
+    wl = scenes.WORKLOADS["ffr_vs_tffr_c64"]
+    k, ku = scenes.radar_sampling(wl.n_pulses, wl.n_freq)
+    prm = T.default_params(n_pulses=wl.n_pulses, n_freq=wl.n_freq, mx=wl.m, my=wl.m, fov_x=wl.fov, fov_y=wl.fov,
+                           gridding=T.GRID_LITERAL)
+    assert T.Plan(prm, k, ku, DEV).range_mode == 0
 
 
 def test_full_swath_sampled_columns_and_memory():

@@ -70,9 +70,9 @@ def test_range_gridding_stage(weighting):
     assert rel_l2(got, ref) < 2e-6
 
 
-# Dense slices (consecutive samples ~0.3-1.3 fine cells apart at fov 40 m) go to the
-# sliding-window range kernel, sparse ones to the sub-pass kernel; TFFR_RANGE_MODE forces
-# either at plan creation.  Rows wider than the fine row are cut into several parts.
+# Dense slices (consecutive samples ~0.3-1.3 fine cells apart at fov 40 m) through both
+# range kernels: TFFR_RANGE_MODE forces the sub-pass (0) or the run kernel (1) at plan
+# creation.  Rows wider than the fine row are cut into several parts.
 DENSE = [(6, 256, 32), (4, 1000, 64), (3, 777, 128)]
 
 
@@ -88,6 +88,26 @@ def test_range_gridding_modes_dense(size, mode, monkeypatch):
     c = OP.weighted_samples(case.prob, s, case.rounded(phase))
     ref = es_spread_rows_cpu(case, c)
     assert rel_l2(got, ref) < 2e-6
+
+
+# The run kernel at rows long enough for several waves of runs (NT = 256 on a 2048-cell
+# row: the first run of each wave goes through its halo) and for several parts (span
+# beyond the row at fov 300 m), dense and sparse, in both precisions.
+@pytest.mark.parametrize("n_freq,fov,dtype", [(4000, 200.0, T.C64), (6000, 300.0, T.C64), (600, 200.0, T.C64),
+                                              (4000, 200.0, T.C128), (6000, 300.0, T.C128)])
+def test_range_gridding_run_kernel_many_waves(n_freq, fov, dtype, monkeypatch):
+    print(f"gridding stage, run kernel n_freq={n_freq} fov={fov} dtype={dtype}", flush=True)
+    monkeypatch.setenv("TFFR_RANGE_MODE", "1")
+    case = Case(2, n_freq, 1024, fov=fov, weighting=T.W_TFFR, dtype=dtype, seed=17)
+    assert case.plan.range_mode == 1 and case.plan.nfine[0] == 2048
+    s, st = case.samples()
+    phase = case.rng.normal(0, 0.5, 2)
+    got = case.plan.tffr_debug_rows(st, stage=0, phase=case.real(phase)).cpu().numpy()
+    c = OP.weighted_samples(case.prob, s, case.rounded(phase))
+    ref = es_spread_rows_cpu(case, c)
+    err = rel_l2(got, ref)
+    print(f"  rel-L2 {err:.3e}", flush=True)
+    assert err < (2e-6 if dtype == T.C64 else 1e-11)
 
 
 @pytest.mark.parametrize("mode", ["0", "1"])
