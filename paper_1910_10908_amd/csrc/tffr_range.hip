@@ -134,6 +134,18 @@ __device__ __forceinline__ void run_taps(cplx<R>* dst, R z0, R dz, R beta, cplx<
   for (int i = 0; i < WW; ++i) dst[i] = v[i] + es_kernel(z0 + (R)i * dz, beta) * c;
 }
 
+// sum_i phi_i dst[i] over the WW taps of one sample: the cells are read back to back.
+template <int WW, typename R>
+__device__ __forceinline__ cplx<R> gather_taps(const cplx<R>* src, R z0, R dz, R beta) {
+  cplx<R> v[WW];
+#pragma unroll
+  for (int i = 0; i < WW; ++i) v[i] = src[i];
+  cplx<R> a = {0, 0};
+#pragma unroll
+  for (int i = 0; i < WW; ++i) a = a + es_kernel(z0 + (R)i * dz, beta) * v[i];
+  return a;
+}
+
 template <typename R, int LOGN, int NT, int WM>
 __global__ __launch_bounds__(NT) void k_fwd_rows_run(Geo g, Tab<R> t, int stype, const void* __restrict__ samples,
                                                      const R* __restrict__ phase, const R* __restrict__ dalong,
@@ -252,10 +264,11 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
                                                  cplx<R>* __restrict__ grad_s, R* __restrict__ grad_phase,
                                                  R* __restrict__ grad_dalong, EntComb<R> ec) {
   constexpr int N = 1 << LOGN;
+  constexpr int PAD = 2 * kRunWindow;
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
-  cplx<R>* buf = tw + tw_entries<N>();
-  float* lpoly = reinterpret_cast<float*>(buf + N);
+  cplx<R>* buf = tw + tw_entries<N>();  // [N + PAD]: the row, then a copy of its first PAD cells
+  float* lpoly = reinterpret_cast<float*>(buf + N + PAD);
   cplx<R>* gbuf = reinterpret_cast<cplx<R>*>(lpoly + kPolyLds);  // FFR only: interpolated values
   const int n = blockIdx.x;
   const int mx = g.mx;
@@ -311,6 +324,9 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
   const R halfw = (R)(0.5 * g.W), inv_halfw = (R)(2.0 / g.W), beta = es_shape<R>(g);
   __syncthreads();
   lds_fft<-1, N, NT, 1, 8, 1>(buf, tw);
+  // the row's first cells once more past its end, so a sample's taps are W consecutive cells
+  if (threadIdx.x < PAD) buf[N + threadIdx.x] = buf[threadIdx.x];
+  __syncthreads();
   double acc_phase = 0.0;
   for (int p = threadIdx.x; p < g.n_freq; p += NT) {
     const double kp = k_next;
@@ -335,11 +351,27 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
       R f;
       fine_pos<R>(kx * g.tx_scale, N, ui, f);
       const int k0 = (int)ceil(f - halfw);
-      const int cell = ui + k0;
+      const cplx<R>* src = buf + ((ui + k0) & (N - 1));
       const R z0 = ((R)k0 - f) * inv_halfw;
-      for (int i = 0; i < g.W; ++i) {
-        const R phi = es_kernel(z0 + (R)i * inv_halfw, beta);
-        a = a + phi * buf[(cell + i) & (N - 1)];
+      if (g.W <= kRunWindow) {
+        switch (g.W) {  // uniform: one unrolled tap block per kernel width
+#define TFFR_ADJ_TAPS(WW) \
+  case WW: a = gather_taps<WW>(src, z0, inv_halfw, beta); break;
+          TFFR_ADJ_TAPS(2)
+          TFFR_ADJ_TAPS(3)
+          TFFR_ADJ_TAPS(4)
+          TFFR_ADJ_TAPS(5)
+          TFFR_ADJ_TAPS(6)
+          TFFR_ADJ_TAPS(7)
+          TFFR_ADJ_TAPS(8)
+#undef TFFR_ADJ_TAPS
+        }
+      } else {
+        const int cell = ui + k0;
+        for (int i = 0; i < g.W; ++i) {
+          const R phi = es_kernel(z0 + (R)i * inv_halfw, beta);
+          a = a + phi * buf[(cell + i) & (N - 1)];
+        }
       }
     }
     if (ffr) {
@@ -420,7 +452,7 @@ template <typename R>
 hipError_t launch_adj_rows(const Geo& g, const Tab<R>& t, int stype, const cplx<R>* hx, const void* samples,
                            const R* phase, const R* dalong, const R* w, cplx<R>* grad_s, R* grad_phase,
                            R* grad_dalong, const EntComb<R>& ec, hipStream_t st) {
-  size_t lds = sizeof(cplx<R>) * (((size_t)1 << g.lognfx) + ((size_t)1 << g.lognfx) / 64 + 64) +
+  size_t lds = sizeof(cplx<R>) * (((size_t)1 << g.lognfx) + 2 * kRunWindow + ((size_t)1 << g.lognfx) / 64 + 64) +
                sizeof(float) * kPolyLds;
   if (g.weighting == 2) lds += sizeof(cplx<R>) * (size_t)g.n_freq;
   TFFR_LOGN_DISPATCH(g.lognfx, {
