@@ -249,7 +249,7 @@ def sweep(args):
             rec[label] = {"ms_per_step": ms, "Msamples_per_s": wl.n_samples / (ms * 1e-3) / 1e6,
                           "timing": "hip_graph" if ms_g < ms_e else "eager"}
             if wt == T.W_TFFR:
-                rec[label]["range_kernel"] = "k_fwd_rows_run" if plan.range_mode == 1 else "k_fwd_rows"
+                rec[label]["range_kernel"] = "k_fwd_rows_run" if plan.range_mode >= 1 else "k_fwd_rows"
                 torch.cuda.synchronize()
                 torch.cuda.reset_peak_memory_stats()
                 st()

@@ -519,15 +519,18 @@ bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 // kernels and the literal lattice taps.
 
 void range_schedule(const tffr_params* p, const HostKx& kx, int nfx, int W, int nt, int* S, int* part_len,
-                    int* mode) {
+                    int* mode, int* pair) {
   const double tx = p->fov_x / (2.0 * kPi * p->mx);
   const int P = p->n_freq;
-  double smin = 1e300;
+  double smin = 1e300, smax = 0.0;
   int Q = 1;
   std::vector<double> U(P);
   for (int n = 0; n < p->n_pulses; ++n) {
     for (int i = 0; i < P; ++i) U[i] = kx(n, i) * tx * nfx;
-    for (int i = 0; i + 1 < P; ++i) smin = std::min(smin, U[i + 1] - U[i]);
+    for (int i = 0; i + 1 < P; ++i) {
+      smin = std::min(smin, U[i + 1] - U[i]);
+      smax = std::max(smax, U[i + 1] - U[i]);
+    }
     for (;; ++Q) {
       const int len = (P + Q - 1) / Q;
       bool ok = true;
@@ -551,6 +554,12 @@ void range_schedule(const tffr_params* p, const HostKx& kx, int nfx, int W, int 
     if (v == 0 || (v == 1 && W <= tffr::kRunWindow)) m = v;
   }
   *mode = m;
+  // on complex64 rows of 4096 cells and more with samples under half a cell apart (so two
+  // consecutive samples' first cells differ by at most one) the run kernel takes its
+  // samples two at a time, summing both samples' taps in registers over W + 1 cells; then
+  // samples S - 1 apart must keep the same clearance
+  *pair = (m == 1 && W == 7 && P > 1 && p->dtype != TFFR_C128 && nfx >= 4096 && smax < 0.5) ? 1 : 0;
+  if (*pair) *S = std::min(P, *S + 1);
   int len = (P + Q - 1) / Q;
   if (m == 1) len = std::min(len, nt * *S);
   *part_len = len;
@@ -758,7 +767,7 @@ tffr_status plan_create(const tffr_params* p, const double* k, const double* ku,
   g.yemax = yemax;
   const HostKx hkx{k, ku, kx_tab, p->n_freq};
   range_schedule(p, hkx, nfx, lit ? 2 * (int)p->q : W, tffr::rows_threads(lognx), &g.sub, &g.part_len,
-                 &g.range_mode);
+                 &g.range_mode, &g.run_pair);
   std::vector<double> dx = deapod_table(p->mx, nfx, W, P->beta), dy = deapod_table(p->my, nfy, W, P->beta);
   if (lit)  // divide by the window w(u) = exp(-a |u|), u = X / fov_x (Algorithm 1)
     for (int j = 0; j < p->mx; ++j) dx[j] = std::exp(p->window_a * std::fabs((j - p->mx / 2) / (double)p->mx));
@@ -1203,7 +1212,7 @@ tffr_status tffr_debug_ffr_route(const tffr_plan* P, int32_t* route, int32_t* la
 
 tffr_status tffr_debug_plan_config(const tffr_plan* P, int32_t* range_mode, int32_t* az_cols, int32_t* ent_fused) {
   if (!P) return TFFR_ERR_ARG;
-  if (range_mode) *range_mode = P->geo.range_mode;
+  if (range_mode) *range_mode = P->geo.range_mode == 1 && P->geo.run_pair ? 2 : P->geo.range_mode;
   if (az_cols) *az_cols = P->cb;
   if (ent_fused) *ent_fused = P->ent_fused ? 1 : 0;
   return TFFR_OK;

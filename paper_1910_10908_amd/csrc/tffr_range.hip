@@ -134,6 +134,28 @@ __device__ __forceinline__ void run_taps(cplx<R>* dst, R z0, R dz, R beta, cplx<
   for (int i = 0; i < WW; ++i) dst[i] = v[i] + es_kernel(z0 + (R)i * dz, beta) * c;
 }
 
+// The taps of two consecutive samples whose first cells are c0 and c0 + d1 (d1 0 or 1),
+// summed in registers and read-add-written once over the WW + 1 cells from c0.
+template <int WW, typename R>
+__device__ __forceinline__ void run_taps_pair(cplx<R>* dst, R za, R zb, bool d1, R dz, R beta, cplx<R> ca,
+                                              cplx<R> cb) {
+  cplx<R> v[WW + 1];
+#pragma unroll
+  for (int i = 0; i <= WW; ++i) v[i] = dst[i];
+  R pa[WW], pb[WW];
+#pragma unroll
+  for (int i = 0; i < WW; ++i) {
+    pa[i] = es_kernel(za + (R)i * dz, beta);
+    pb[i] = es_kernel(zb + (R)i * dz, beta);
+  }
+#pragma unroll
+  for (int k = 0; k <= WW; ++k) {
+    const R ta = k < WW ? pa[k] : (R)0;
+    const R tb = d1 ? (k >= 1 ? pb[k - 1] : (R)0) : (k < WW ? pb[k] : (R)0);
+    dst[k] = v[k] + ta * ca + tb * cb;
+  }
+}
+
 // sum_i phi_i dst[i] over the WW taps of one sample: the cells are read back to back.
 template <int WW, typename R>
 __device__ __forceinline__ cplx<R> gather_taps(const cplx<R>* src, R z0, R dz, R beta) {
@@ -146,8 +168,22 @@ __device__ __forceinline__ cplx<R> gather_taps(const cplx<R>* src, R z0, R dz, R
   return a;
 }
 
-template <typename R, int LOGN, int NT, int WM>
-__global__ __launch_bounds__(NT) void k_fwd_rows_run(Geo g, Tab<R> t, int stype, const void* __restrict__ samples,
+// waves per SIMD the paired run kernel's registers are sized for (complex64): the
+// workgroups per CU its LDS row allows (160 KB per CU), at most four waves
+template <typename R, int LOGN, int NT, bool PAIR>
+constexpr int run_waves() {
+  if constexpr (sizeof(R) != 4 || !PAIR) {
+    return 1;
+  } else {
+    constexpr int wg = (160 * 1024) / ((int)sizeof(cplx<R>) * ((1 << LOGN) + 512) + 4096);
+    constexpr int w = (wg < 1 ? 1 : wg) * (NT / 64) / 4;
+    return w < 1 ? 1 : (w > 4 ? 4 : w);
+  }
+}
+
+template <typename R, int LOGN, int NT, int WM, bool PAIR>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(run_waves<R, LOGN, NT, PAIR>())))
+void k_fwd_rows_run(Geo g, Tab<R> t, int stype, const void* __restrict__ samples,
                                                      const R* __restrict__ phase, const R* __restrict__ dalong,
                                                      const R* __restrict__ w, cplx<R>* __restrict__ out,
                                                      int stage) {
@@ -178,28 +214,21 @@ __global__ __launch_bounds__(NT) void k_fwd_rows_run(Geo g, Tab<R> t, int stype,
     const int p0 = pa + S * (int)threadIdx.x;
     const int p1 = min(p0 + S, pb);
     int cfirst = 0;
-    double k_nx = p0 < p1 ? raw_k(t, g.n_freq, n, p0) : 0.0;
-    cplx<R> s_nx = (p0 < p1 && !ffr) ? load_sample<R>(samples, stype, base_s + p0) : cplx<R>{0, 0};
-    for (int p = p0; p < p1; ++p) {
-      const double kp = k_nx;
-      const cplx<R> sp = s_nx;
-      if (p + 1 < p1) {
-        k_nx = raw_k(t, g.n_freq, n, p + 1);
-        if (!ffr) s_nx = load_sample<R>(samples, stype, base_s + p + 1);
-      }
+    // one sample's weighted value, first tap cell (unwrapped: only differences and the low
+    // LOGN bits are used), kernel offset and fraction; false if the threshold removed it
+    auto prep = [&](int p, double kp, cplx<R> sp, int& c0, int& k0, R& f, cplx<R>& c) {
       const double kx = kx_of(t, kp, ku);
       const double lam = lattice_coord(kx, g);
       bool kept;
-      const cplx<R> c = weighted_sample<R>(g, t, poly, stype, samples, w, n, p, ku, lam, rot, sp, kept);
+      c = weighted_sample<R>(g, t, poly, stype, samples, w, n, p, ku, lam, rot, sp, kept);
       const double tt = kx * g.tx_scale;
       int ui;
-      R f;
       fine_pos<R>(tt, N, ui, f);
-      const int k0 = (int)ceil(f - halfw);
-      // unwrapped first tap cell (only differences and the low LOGN bits are used)
-      const int c0 = (int)((unsigned)(int)floor(tt) * (unsigned)N + (unsigned)(ui + k0));
-      if (p == p0) cfirst = c0;
-      if (!kept) continue;  // removed by the threshold: no taps
+      k0 = (int)ceil(f - halfw);
+      c0 = (int)((unsigned)(int)floor(tt) * (unsigned)N + (unsigned)(ui + k0));
+      return kept;
+    };
+    auto single = [&](int c0, int k0, R f, cplx<R> c) {
       const int rel = c0 - cfirst;
       cplx<R>* dst = (lane == 0 && rel < W) ? halo + wv * PAD + rel : buf + (c0 & (N - 1));
       const R z0 = ((R)k0 - f) * inv_halfw;
@@ -214,6 +243,71 @@ __global__ __launch_bounds__(NT) void k_fwd_rows_run(Geo g, Tab<R> t, int stype,
         TFFR_RUN_TAPS(7)
         TFFR_RUN_TAPS(8)
 #undef TFFR_RUN_TAPS
+      }
+    };
+    if constexpr (!PAIR) {
+      double k_nx = p0 < p1 ? raw_k(t, g.n_freq, n, p0) : 0.0;
+      cplx<R> s_nx = (p0 < p1 && !ffr) ? load_sample<R>(samples, stype, base_s + p0) : cplx<R>{0, 0};
+      for (int p = p0; p < p1; ++p) {
+        const double kp = k_nx;
+        const cplx<R> sp = s_nx;
+        if (p + 1 < p1) {
+          k_nx = raw_k(t, g.n_freq, n, p + 1);
+          if (!ffr) s_nx = load_sample<R>(samples, stype, base_s + p + 1);
+        }
+        int c0, k0;
+        R f;
+        cplx<R> c;
+        const bool kept = prep(p, kp, sp, c0, k0, f, c);
+        if (p == p0) cfirst = c0;
+        if (kept) single(c0, k0, f, c);  // a removed sample has no taps
+      }
+    } else {
+      // samples two at a time (the plan's S keeps samples S - 1 apart more than W cells
+      // apart, so the two samples of every lane in a step stay clear of the other lanes')
+      double ka = 0.0, kb = 0.0;
+      cplx<R> sa = {0, 0}, sb = {0, 0};
+      if (p0 < p1) {
+        ka = raw_k(t, g.n_freq, n, p0);
+        if (!ffr) sa = load_sample<R>(samples, stype, base_s + p0);
+      }
+      if (p0 + 1 < p1) {
+        kb = raw_k(t, g.n_freq, n, p0 + 1);
+        if (!ffr) sb = load_sample<R>(samples, stype, base_s + p0 + 1);
+      }
+      for (int p = p0; p < p1; p += 2) {
+        const double kpa = ka, kpb = kb;
+        const cplx<R> spa = sa, spb = sb;
+        if (p + 2 < p1) {
+          ka = raw_k(t, g.n_freq, n, p + 2);
+          if (!ffr) sa = load_sample<R>(samples, stype, base_s + p + 2);
+        }
+        if (p + 3 < p1) {
+          kb = raw_k(t, g.n_freq, n, p + 3);
+          if (!ffr) sb = load_sample<R>(samples, stype, base_s + p + 3);
+        }
+        int c0a, k0a;
+        R fa;
+        cplx<R> ca;
+        const bool kept_a = prep(p, kpa, spa, c0a, k0a, fa, ca);
+        if (p == p0) cfirst = c0a;
+        const bool has_b = p + 1 < p1;
+        int c0b = c0a, k0b = 0;
+        R fb = 0;
+        cplx<R> cb = {0, 0};
+        bool kept_b = false;
+        if (has_b) kept_b = prep(p + 1, kpb, spb, c0b, k0b, fb, cb);
+        const int d = c0b - c0a;
+        if (W == 7 && has_b && (d == 0 || d == 1) && (kept_a || kept_b)) {
+          // removed samples carry a zero value here
+          const int rel = c0a - cfirst;
+          cplx<R>* dst = (lane == 0 && rel < W) ? halo + wv * PAD + rel : buf + (c0a & (N - 1));
+          run_taps_pair<7>(dst, ((R)k0a - fa) * inv_halfw, ((R)k0b - fb) * inv_halfw, d == 1, inv_halfw, beta,
+                           kept_a ? ca : cplx<R>{0, 0}, kept_b ? cb : cplx<R>{0, 0});
+        } else {
+          if (kept_a) single(c0a, k0a, fa, ca);
+          if (kept_b) single(c0b, k0b, fb, cb);
+        }
       }
     }
     if (lane == 0) hcf[wv] = p0 < p1 ? (cfirst & (N - 1)) : -1;
@@ -409,6 +503,16 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
 }
 
 // ============================================================================ launchers
+// the run kernel, paired (complex64 rows of 4096 cells and more, the plan's choice for
+// samples under half a cell apart) or one sample at a time
+template <typename R, int L, int NT>
+static auto run_kernel(bool pair) {
+  if constexpr (sizeof(R) == 4 && L >= 12) {
+    if (pair) return k_fwd_rows_run<R, L, NT, kRunWindow, true>;
+  }
+  return k_fwd_rows_run<R, L, NT, kRunWindow, false>;
+}
+
 #ifdef TFFR_EMIT_SHARED
 int rows_threads(int logn) {
   switch (logn) {
@@ -438,7 +542,7 @@ hipError_t launch_fwd_rows(const Geo& g, const Tab<R>& t, int stype, const void*
     // run kernel: the row's pad and one halo per wave, 2 kRunWindow cells each
     if (g.range_mode == 1) lds += sizeof(cplx<R>) * (size_t)(2 * kRunWindow) * (1 + NT / 64) + sizeof(int) * kRunHaloInts;
     auto fn = g.range_mode == 1
-                  ? k_fwd_rows_run<R, L, NT, kRunWindow>
+                  ? run_kernel<R, L, NT>(g.run_pair != 0)
                   : (g.sub <= 4 ? k_fwd_rows<R, L, NT, 4>
                                 : (g.sub <= 8 ? k_fwd_rows<R, L, NT, 8> : k_fwd_rows<R, L, NT, 16>));
     hipError_t e = allow_lds((const void*)fn, lds);

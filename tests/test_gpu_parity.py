@@ -90,16 +90,19 @@ def test_range_gridding_modes_dense(size, mode, monkeypatch):
     assert rel_l2(got, ref) < 2e-6
 
 
-# The run kernel at rows long enough for several waves of runs (NT = 256 on a 2048-cell
-# row: the first run of each wave goes through its halo) and for several parts (span
-# beyond the row at fov 300 m), dense and sparse, in both precisions.
-@pytest.mark.parametrize("n_freq,fov,dtype", [(4000, 200.0, T.C64), (6000, 300.0, T.C64), (600, 200.0, T.C64),
-                                              (4000, 200.0, T.C128), (6000, 300.0, T.C128)])
-def test_range_gridding_run_kernel_many_waves(n_freq, fov, dtype, monkeypatch):
-    print(f"gridding stage, run kernel n_freq={n_freq} fov={fov} dtype={dtype}", flush=True)
+# The run kernel at rows long enough for several waves of runs (NT = 256 on 2048- and
+# 4096-cell rows: the first run of each wave goes through its halo) and for several parts
+# (span beyond the row), dense and sparse, in both precisions; on 4096-cell complex64 rows
+# with samples under half a cell apart, its paired form (range mode 2).
+@pytest.mark.parametrize("n_freq,fov,mx,dtype,mode", [
+    (4000, 200.0, 1024, T.C64, 1), (6000, 300.0, 1024, T.C64, 1), (600, 200.0, 1024, T.C64, 1),
+    (4000, 200.0, 1024, T.C128, 1), (6000, 300.0, 1024, T.C128, 1),
+    (6600, 300.0, 2048, T.C64, 2), (13000, 600.0, 2048, T.C64, 2), (13000, 600.0, 2048, T.C128, 1)])
+def test_range_gridding_run_kernel_many_waves(n_freq, fov, mx, dtype, mode, monkeypatch):
+    print(f"gridding stage, run kernel n_freq={n_freq} fov={fov} mx={mx} dtype={dtype}", flush=True)
     monkeypatch.setenv("TFFR_RANGE_MODE", "1")
-    case = Case(2, n_freq, 1024, fov=fov, weighting=T.W_TFFR, dtype=dtype, seed=17)
-    assert case.plan.range_mode == 1 and case.plan.nfine[0] == 2048
+    case = Case(2, n_freq, mx, fov=fov, weighting=T.W_TFFR, dtype=dtype, seed=17)
+    assert case.plan.range_mode == mode and case.plan.nfine[0] == 2 * mx
     s, st = case.samples()
     phase = case.rng.normal(0, 0.5, 2)
     got = case.plan.tffr_debug_rows(st, stage=0, phase=case.real(phase)).cpu().numpy()
