@@ -17,6 +17,10 @@ stationary phase the azimuth transform of one scatterer's echo carries the phase
 the scene-centre range and leaves a exp(-i (kx x + ky y)), ky = ku: the samples the
 image formation of Eq. (1) sums, on the Stolt coordinates of the geometry module.
 
+Per-pulse position errors: when the platform recorded echo j at u_j + du_j instead of its
+nominal position, the same sum taken at the true positions is the exact azimuth transform
+(it is no longer a DFT); the scatterer's phase model above then holds unchanged.
+
 Stolt baseline (Sec. II-A; Sec. IV, Baselines): along every azimuth slice the samples,
 non-uniform in kx, are interpolated linearly onto the uniform range grid
 kx = 2 pi l / fov_x (integer l, the lattice of Algorithm 1), zero outside the slice's
@@ -41,15 +45,20 @@ def azimuth_wavenumbers(n_pulses, n_positions, du):
     return (np.arange(n_pulses, dtype=np.float64) - n_pulses / 2.0) * (2.0 * np.pi / (n_positions * du))
 
 
-def front_end(echoes, k, du, xc, n_pulses):
+def front_end(echoes, k, du, xc, n_pulses, dpos=None):
     """Azimuth transform of raw echoes and reference-function multiply (see module doc).
 
     echoes: [J, n_freq] complex, k: [n_freq] rad/m, du: position step (m), xc: reference
-    range (m).  Returns (s [n_pulses, n_freq] complex128, ku [n_pulses]).
+    range (m), dpos: [J] along-track position errors (m) or None.  With dpos the echo of
+    position j was recorded at u_j + dpos[j], and the azimuth sum is taken at those true
+    positions (a non-uniform transform; the wavenumbers ku_n stay those of the nominal
+    grid).  Returns (s [n_pulses, n_freq] complex128, ku [n_pulses]).
     """
     e = np.asarray(echoes, dtype=np.complex128)
     J = e.shape[0]
     u = (np.arange(J, dtype=np.float64) - J / 2.0) * du
+    if dpos is not None:
+        u = u + np.asarray(dpos, dtype=np.float64)
     ku = azimuth_wavenumbers(n_pulses, J, du)
     F = np.exp(-1j * np.outer(ku, u))  # [n, j]
     kx, _ = geometry.stolt(k, ku)

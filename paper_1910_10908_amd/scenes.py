@@ -87,11 +87,14 @@ def rma_positions(n_pulses, fc=10e9):
     return 2 * n_pulses, C_LIGHT / (4.0 * fc)
 
 
-def raw_echoes(k, n_positions, du, xc, x, y, a, chunk=16):
+def raw_echoes(k, n_positions, du, xc, x, y, a, chunk=16, dpos=None):
     """Point-scatterer raw echoes e[j, p] = sum_t a_t exp(-2 i k_p R_t(u_j)) (FP64 numpy),
-    R_t(u) = sqrt((xc + x_t)^2 + (y_t - u)^2), u_j = (j - J/2) du."""
+    R_t(u) = sqrt((xc + x_t)^2 + (y_t - u)^2), u_j = (j - J/2) du (+ dpos[j]: the
+    platform's along-track position error at position j, when given)."""
     k = np.asarray(k, dtype=np.float64)
     u = (np.arange(n_positions, dtype=np.float64) - n_positions / 2.0) * du
+    if dpos is not None:
+        u = u + np.asarray(dpos, dtype=np.float64)
     out = np.zeros((n_positions, k.size), dtype=np.complex128)
     for t0 in range(0, len(x), chunk):
         for t in range(t0, min(t0 + chunk, len(x))):

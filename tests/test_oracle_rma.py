@@ -74,6 +74,37 @@ def test_front_end_focuses_a_point_scatterer(method):
     assert not (abs(x - xt) <= px and abs(y - yt) <= py)
 
 
+def test_front_end_position_errors_tone():
+    """Per-pulse position errors: an azimuth tone exp(+i ku_m u) recorded at the true
+    positions u_j + d_j transforms to exactly J at bin m (every term of the sum is 1) when
+    the front end is given d; taken at the nominal positions instead, bin m is off by the
+    unmodelled phases."""
+    n_pulses, n_freq = 32, 4
+    k, _, J, du = _small_rma(n_pulses, n_freq)
+    rng = np.random.default_rng(21)
+    d = rng.uniform(-0.4, 0.4, J) * du
+    ku = rma.azimuth_wavenumbers(n_pulses, J, du)
+    m = 30  # near the band edge, where ku d is largest
+    u = (np.arange(J) - J / 2.0) * du + d
+    e = np.repeat(np.exp(1j * ku[m] * u)[:, None], n_freq, axis=1)
+    s, _ = rma.front_end(e, k, du, 0.0, n_pulses, dpos=d)
+    np.testing.assert_allclose(s[m], J, rtol=0, atol=1e-9 * J)
+    s0, _ = rma.front_end(e, k, du, 0.0, n_pulses)
+    assert np.abs(s0[m] - J).min() > 0.02 * J
+
+
+def test_front_end_uniform_position_shift():
+    """A uniform error d at every position multiplies bin n by exp(-i ku_n d): the sign
+    and the scale with which the errors enter the azimuth phase."""
+    k, _, J, du = _small_rma(32, 12)
+    rng = np.random.default_rng(22)
+    e = rng.standard_normal((J, 12)) + 1j * rng.standard_normal((J, 12))
+    d = 0.37 * du
+    s0, ku = rma.front_end(e, k, du, 5.0, 32)
+    s1, _ = rma.front_end(e, k, du, 5.0, 32, dpos=np.full(J, d))
+    np.testing.assert_allclose(s1, np.exp(-1j * ku * d)[:, None] * s0, rtol=0, atol=1e-10 * np.abs(s0).max())
+
+
 def test_stolt_interpolation_is_exact_on_linear_data():
     """Linear interpolation reproduces a linear function of lam exactly, and returns the
     samples themselves where they sit on integers."""
