@@ -465,6 +465,31 @@ def stolt_and_front_end(T, torch, wl, plan, k, ku, s, s_np, acc_cols, ms_step, a
         rec["accuracy"] = dict(accuracy(smp[:, ct].cpu().numpy().astype(np.complex128), ref),
                                sample=f"{len(cols)} of {wl.n_freq} fast-time columns, all pulses")
     res["rma_front_end"] = rec
+    # the same front end with per-pulse along-track position errors: a smooth platform
+    # drift of up to 0.4 du (three random-phase sinusoids over the aperture), so the true
+    # positions stay about du apart; a type-1 NUFFT along azimuth instead of the FFT.  The
+    # call copies the positions after synchronising its stream, so it is timed eagerly,
+    # with the copy.
+    log("comparison: rma_front_end with position errors")
+    rng_d = np.random.default_rng(18)
+    jj = np.arange(J) / J
+    drift = sum(np.sin(2 * np.pi * (f * jj + rng_d.uniform())) / f for f in (1.0, 2.0, 3.0))
+    dpos = 0.4 * du * drift / np.max(np.abs(drift))
+    ms_fp, _ = time_step(torch, lambda: plan.tffr_rma_front_end(echoes, du, xc, out=smp, dpos=dpos), steps, 5,
+                         graph=False)
+    rec = {"ms": ms_fp, "raw_positions": J, "Msamples_per_s": wl.n_samples / (ms_fp * 1e-3) / 1e6,
+           "over_uniform_front_end": ms_fp / ms_fe,
+           "note": "echoes recorded at u_j + d_j, a smooth drift with |d_j| <= 0.4 du: ES spreading of the J "
+                   "echoes at their true positions onto a periodic grid of >= 2 N_u cells (sub-passes), FFT, "
+                   "deapodisation, reference multiply; eager launches including the per-call position copy"}
+    if not args.no_cpu_baseline:
+        from oracle import rma as ORMA
+
+        plan.tffr_rma_front_end(echoes, du, xc, out=smp, dpos=dpos)
+        ref, _ = ORMA.front_end(ein, k[cols], du, xc, wl.n_pulses, dpos=dpos)
+        rec["accuracy"] = dict(accuracy(smp[:, ct].cpu().numpy().astype(np.complex128), ref),
+                               sample=f"{len(cols)} of {wl.n_freq} fast-time columns, all pulses")
+    res["rma_front_end_position_errors"] = rec
     return res
 
 

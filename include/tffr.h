@@ -195,6 +195,21 @@ tffr_status tffr_forward(tffr_plan *plan, const void *d_samples, const void *d_p
 tffr_status tffr_rma_front_end(tffr_plan *plan, const void *d_echoes, int32_t n_positions, double du,
                                double xc, void *d_samples, tffr_stream stream);
 
+/* The same front end for echoes recorded off their nominal positions (per-pulse
+ * along-track position errors): echo j was recorded at u_j + dpos[j], and the azimuth sum
+ *   d_samples[n][p] = exp(+i kx(n, p) xc) sum_j d_echoes[j][p] exp(-i ku_n (u_j + dpos[j]))
+ * is taken at those true positions (no longer a DFT: a type-1 NUFFT at the positions,
+ * ES kernel of the plan's width on a periodic grid of at least 2 n_pulses cells).
+ *   dpos  HOST array [n_positions] of position errors in metres, finite; the true
+ *         positions must increase strictly with j and stay within one period n_positions du
+ *         (else TFFR_ERR_NONMONOTONE).
+ * Other arguments and their errors as tffr_rma_front_end.  The positions are copied to a
+ * plan-owned device buffer: the call first synchronises `stream` (an earlier call's launch
+ * may still read the buffer), then enqueues the transform.  Calls on one plan from
+ * different host threads must not overlap. */
+tffr_status tffr_rma_front_end_pos(tffr_plan *plan, const void *d_echoes, int32_t n_positions, double du,
+                                   const double *dpos, double xc, void *d_samples, tffr_stream stream);
+
 /* Stolt-interpolation baseline image (Sec. II-A; Sec. IV, Baselines): along every slice
  * the (phased) samples are interpolated linearly onto the integer lattice l between the
  * slice's first and last sample (kx = 2 pi l / fov_x; zero outside), and

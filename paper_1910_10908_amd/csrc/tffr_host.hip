@@ -171,7 +171,10 @@ struct tffr_plan {
   int stolt_part = 0;        // Stolt baseline: samples per part (span below mx - 1 lattice units)
   double beta = 0.0;
   // device tables
-  DevBuf k, ku, kx, ky, ystart, ytap, deapx, deapy, twx, twy, poly, ffr_d, ycn, ycw;
+  DevBuf k, ku, kx, ky, ystart, ytap, deapx, deapy, twx, twy, poly, ffr_d, ycn, ycw, deapf;
+  int logfg = 0;           // front end with position errors: log2 of its periodic grid (>= 2 n_pulses)
+  DevBuf fpos;             // its source positions on that grid (FP64), refreshed by every call
+  size_t fpos_n = 0;
   // workspace layout
   bool ent_fused = false;  // entropy step uses the fused azimuth kernel
   int coord_cb = 0;        // azimuth block width of the coordinate-gradient kernels (0: unsupported)
@@ -214,6 +217,7 @@ tffr::Tab<R> tables(const tffr_plan* P) {
   t.twx = (const cplx<R>*)P->twx.p;
   t.twy = (const cplx<R>*)P->twy.p;
   t.poly = (const float*)P->poly.p;
+  t.deapf = (const R*)P->deapf.p;
   t.ycell_n = (const int32_t*)P->ycn.p;
   t.ycell_w = (const R*)P->ycw.p;
   return t;
@@ -769,6 +773,10 @@ tffr_status plan_create(const tffr_params* p, const double* k, const double* ku,
   range_schedule(p, hkx, nfx, lit ? 2 * (int)p->q : W, tffr::rows_threads(lognx), &g.sub, &g.part_len,
                  &g.range_mode, &g.run_pair);
   std::vector<double> dx = deapod_table(p->mx, nfx, W, P->beta), dy = deapod_table(p->my, nfy, W, P->beta);
+  // front end with position errors: a grid of at least twice the azimuth bins
+  P->logfg = 6;
+  while ((1 << P->logfg) < 2 * p->n_pulses) ++P->logfg;
+  const std::vector<double> df = deapod_table(p->n_pulses, 1 << P->logfg, W, P->beta);
   if (lit)  // divide by the window w(u) = exp(-a |u|), u = X / fov_x (Algorithm 1)
     for (int j = 0; j < p->mx; ++j) dx[j] = std::exp(p->window_a * std::fabs((j - p->mx / 2) / (double)p->mx));
   std::vector<double> twx = twiddle_table(nfx), twy = twiddle_table(nfy);
@@ -778,6 +786,7 @@ tffr_status plan_create(const tffr_params* p, const double* k, const double* ku,
     if (s == TFFR_OK) s = upload(P->ytap, taps);
     if (s == TFFR_OK) s = upload(P->deapx, dx);
     if (s == TFFR_OK) s = upload(P->deapy, dy);
+    if (s == TFFR_OK) s = upload(P->deapf, df);
     if (s == TFFR_OK) s = upload(P->twx, twx);
     if (s == TFFR_OK) s = upload(P->twy, twy);
   } else {
@@ -786,6 +795,7 @@ tffr_status plan_create(const tffr_params* p, const double* k, const double* ku,
     if (s == TFFR_OK) s = upload(P->ytap, cast<float>(taps));
     if (s == TFFR_OK) s = upload(P->deapx, cast<float>(dx));
     if (s == TFFR_OK) s = upload(P->deapy, cast<float>(dy));
+    if (s == TFFR_OK) s = upload(P->deapf, cast<float>(df));
     if (s == TFFR_OK) s = upload(P->twx, cast<float>(twx));
     if (s == TFFR_OK) s = upload(P->twy, cast<float>(twy));
   }
@@ -966,6 +976,52 @@ tffr_status tffr_rma_front_end(tffr_plan* P, const void* echoes, int32_t n_posit
                                                 sample_type(P), samples, st)
                : tffr::launch_rma_front<float>(P->geo, tables<float>(P), logj, (const cplx<float>*)echoes, xc,
                                                sample_type(P), samples, st);
+  return hip_status(e);
+}
+
+tffr_status tffr_rma_front_end_pos(tffr_plan* P, const void* echoes, int32_t n_positions, double du,
+                                   const double* dpos, double xc, void* samples, tffr_stream stream) {
+  if (!P || !echoes || !dpos || !samples) return TFFR_ERR_ARG;
+  if (P->from_xy || !(du > 0.0) || !std::isfinite(du) || !std::isfinite(xc)) return TFFR_ERR_ARG;
+  const int J = n_positions, NU = P->prm.n_pulses;
+  if (J < NU || J < 64 || (J & (J - 1)) != 0) return TFFR_ERR_ARG;
+  const double dku = 2.0 * kPi / ((double)J * du);
+  for (int n = 0; n < NU; ++n)
+    if (std::fabs(P->hku[n] - (n - NU / 2) * dku) > 1e-9 * dku * std::max(1, NU)) return TFFR_ERR_ARG;
+  if (!aligned(echoes, P->csize() / 2) || !aligned(samples, 4)) return TFFR_ERR_LAYOUT;
+  const int G = 1 << P->logfg, W = P->prm.kernel_width;
+  if ((size_t)G * P->csize() + ((size_t)G / 64 + 64) * P->csize() > ((size_t)128 << 10) + 8192)
+    return TFFR_ERR_UNSUPPORTED;
+  // true positions on the periodic grid: g_j = G ((j - J/2) du + d_j) / (J du); strictly
+  // increasing within one period, else TFFR_ERR_NONMONOTONE
+  std::vector<double> gp(J);
+  for (int j = 0; j < J; ++j) {
+    if (!std::isfinite(dpos[j])) return TFFR_ERR_ARG;
+    gp[j] = (double)G * (((double)j - J / 2.0) * du + dpos[j]) / ((double)J * du);
+  }
+  double gmin = gp[0] + G - gp[J - 1];  // the gap across the period
+  for (int j = 1; j < J; ++j) gmin = std::min(gmin, gp[j] - gp[j - 1]);
+  if (!(gmin > 0.0)) return TFFR_ERR_NONMONOTONE;
+  // sub-passes: a power of two (dividing J) with S gmin > W + 1, so sources S apart, also
+  // across the period, keep their taps apart; at most J (one source per sub-pass)
+  int S = 1;
+  while (S < J && S * gmin <= W + 1.0) S *= 2;
+  hipStream_t st = (hipStream_t)stream;
+  // the positions replace those of an earlier call only once its launch has finished
+  if (hipStreamSynchronize(st) != hipSuccess) return TFFR_ERR_HIP;
+  if (P->fpos_n < (size_t)J) {
+    if (P->fpos.p) (void)hipFree(P->fpos.p);
+    P->fpos.p = nullptr;
+    P->fpos_n = 0;
+    if (hipMalloc(&P->fpos.p, sizeof(double) * J) != hipSuccess) return TFFR_ERR_NOMEM;
+    P->fpos_n = J;
+  }
+  if (hipMemcpy(P->fpos.p, gp.data(), sizeof(double) * J, hipMemcpyHostToDevice) != hipSuccess) return TFFR_ERR_HIP;
+  const hipError_t e =
+      P->dbl() ? tffr::launch_rma_front_pos<double>(P->geo, tables<double>(P), P->logfg, (const cplx<double>*)echoes,
+                                                    (const double*)P->fpos.p, J, S, xc, sample_type(P), samples, st)
+               : tffr::launch_rma_front_pos<float>(P->geo, tables<float>(P), P->logfg, (const cplx<float>*)echoes,
+                                                   (const double*)P->fpos.p, J, S, xc, sample_type(P), samples, st);
   return hip_status(e);
 }
 

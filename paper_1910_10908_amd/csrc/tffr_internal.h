@@ -57,6 +57,7 @@ struct Tab {
   const R* deapy;         // [my] 1 / kernel transform, azimuth
   const cplx<R>* twx;     // [nfx/64 + 64] two-level table of exp(+2 pi i m / nfx)
   const cplx<R>* twy;     // [nfy/64 + 64] two-level table of exp(+2 pi i m / nfy)
+  const R* deapf;         // [n_pulses] 1 / kernel transform at the front end's bins n - n_pulses/2 (grid fgrid)
   const int32_t* ycell_n;  // [nfy][yemax] slices whose taps reach each azimuth cell (padded with 0)
   const R* ycell_w;        // [nfy][yemax] the matching kernel taps (padded with 0)
   const float* poly;      // [kPolyDeg+1][kPolySeg] tFFR weight polynomial (float path), or null
@@ -126,6 +127,9 @@ hipError_t launch_entropy(const Geo& g, const cplx<R>* img, double* partials, in
 template <typename R>
 hipError_t launch_rma_front(const Geo& g, const Tab<R>& t, int logj, const cplx<R>* echoes, double xc, int stype,
                             void* out, hipStream_t st);  // tffr_rma.hip
+template <typename R>
+hipError_t launch_rma_front_pos(const Geo& g, const Tab<R>& t, int logg, const cplx<R>* echoes, const double* pos,
+                                int J, int S, double xc, int stype, void* out, hipStream_t st);
 template <typename R>
 hipError_t launch_stolt_rows(const Geo& g, const Tab<R>& t, int stype, const void* samples, const R* phase,
                              const R* dalong, int part, cplx<R>* out, hipStream_t st);

@@ -1,5 +1,5 @@
-// Range-migration front end and Stolt-interpolation baseline of libtffr (Sec. II-A;
-// Sec. IV, Baselines).
+// Range-migration front end (uniform positions, and positions with per-pulse errors) and
+// Stolt-interpolation baseline of libtffr (Sec. II-A; Sec. IV, Baselines).
 //
 // Front end: raw echoes e[j][p] at J along-track positions u_j = (j - J/2) du become the
 // samples s[n][p] = exp(+i kx(n,p) X_c) sum_j e[j][p] exp(-i ku_n u_j), ku_n = (n - N_u/2)
@@ -59,6 +59,67 @@ __global__ __launch_bounds__(NT) void k_rma_front(Geo g, Tab<R> t, const cplx<R>
     const int nn = n - NU / 2;
     cplx<R> v = buf[c * J + (nn & (J - 1))];
     if (nn & 1) v = {-v.x, -v.y};
+    double sn, cs;
+    sincos(stolt_kx(t.k[p], t.ku[n]) * xc, &sn, &cs);
+    v = cmul(v, cplx<R>{(R)cs, (R)sn});
+    const size_t o = (size_t)n * P + p;
+    if (stype == ST_H2) {
+      ((half2s*)out)[o] = {(_Float16)(float)v.x, (_Float16)(float)v.y};
+    } else {
+      ((cplx<R>*)out)[o] = v;
+    }
+  }
+}
+
+// Front end with per-pulse position errors: echo j was recorded at u_j + d_j, so the
+// azimuth sum s[n] = sum_j e[j] exp(-i ku_n (u_j + d_j)) = sum_j e[j] exp(-2 pi i n' t_j),
+// t_j = (u_j + d_j) / (J du), is a type-1 NUFFT at the non-uniform t_j: the echoes are
+// spread with the ES kernel onto a periodic grid of G cells at g_j = G t_j (pos[j]), the
+// grid is transformed forward, and bin n' is divided by the kernel's transform (deapf).
+// A workgroup takes CB fast-time columns; sources are spread in S sub-passes, sub-pass
+// sp taking j = sp, sp + S, ...: S is a power of two (it divides J) with S times the
+// smallest gap between consecutive positions (cyclically) above W + 1 cells, so the taps
+// of one sub-pass never meet and each is a plain read-add-write followed by a barrier.
+template <typename R, int LOGG, int NT, int CB>
+__global__ __launch_bounds__(NT) void k_rma_front_pos(Geo g, Tab<R> t, const cplx<R>* __restrict__ echoes,
+                                                      const double* __restrict__ pos, int J, int S, double xc,
+                                                      int stype, void* __restrict__ out) {
+  constexpr int G = 1 << LOGG;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
+  cplx<R>* buf = tw + tw_entries<G>();  // [CB][G]
+  const int P = g.n_freq, NU = g.n_pulses, W = g.W;
+  const int p0 = xcd_block(blockIdx.x, gridDim.x) * CB;
+  const R halfw = (R)(0.5 * W), inv_halfw = (R)(2.0 / W), beta = es_shape<R>(g);
+  make_twiddles<G, NT>(tw);
+  for (int i = threadIdx.x; i < CB * G; i += NT) buf[i] = {0, 0};
+  __syncthreads();
+  for (int sp = 0; sp < S; ++sp) {
+    for (int j = sp + S * (int)threadIdx.x; j < J; j += S * NT) {
+      cplx<R> e[CB];
+#pragma unroll
+      for (int c = 0; c < CB; ++c) e[c] = p0 + c < P ? echoes[(size_t)j * P + p0 + c] : cplx<R>{0, 0};
+      const double gj = pos[j];
+      const double fl = floor(gj);
+      const R f = (R)(gj - fl);
+      const int k0 = (int)ceil(f - halfw);
+      const int cell = (int)fl + k0;
+      const R z0 = ((R)k0 - f) * inv_halfw;
+      for (int i = 0; i < W; ++i) {
+        const R phi = es_kernel(z0 + (R)i * inv_halfw, beta);
+        const int q = (cell + i) & (G - 1);
+#pragma unroll
+        for (int c = 0; c < CB; ++c) buf[c * G + q] = buf[c * G + q] + phi * e[c];
+      }
+    }
+    __syncthreads();
+  }
+  lds_fft<-1, G, NT, CB, 8, 2>(buf, tw);
+  for (int idx = threadIdx.x; idx < NU * CB; idx += NT) {
+    const int n = idx / CB, c = idx - n * CB, p = p0 + c;
+    if (p >= P) continue;
+    const int nn = n - NU / 2;
+    cplx<R> v = t.deapf[n] * buf[c * G + (nn & (G - 1))];
     double sn, cs;
     sincos(stolt_kx(t.k[p], t.ku[n]) * xc, &sn, &cs);
     v = cmul(v, cplx<R>{(R)cs, (R)sn});
@@ -160,6 +221,42 @@ hipError_t launch_rma_front(const Geo& g, const Tab<R>& t, int logj, const cplx<
 }
 
 template <typename R>
+hipError_t launch_rma_front_pos(const Geo& g, const Tab<R>& t, int logg, const cplx<R>* echoes, const double* pos,
+                                int J, int S, double xc, int stype, void* out, hipStream_t st) {
+  const int G = 1 << logg;
+  // columns per workgroup as for the uniform front end: the widest of 16 ... 1 whose
+  // G x CB row fits 128 KB of LDS and still gives 512 workgroups
+  const size_t col = (size_t)G * sizeof(cplx<R>);
+  int cb = 0;
+  for (int c = 16; c >= 1; c /= 2) {
+    if ((size_t)c * col > ((size_t)128 << 10)) continue;
+    cb = c;
+    if ((g.n_freq + c - 1) / c >= 512) break;
+  }
+  if (cb == 0 || S < 1) return hipErrorInvalidValue;
+  const size_t lds = sizeof(cplx<R>) * ((size_t)G / 64 + 64) + (size_t)cb * col;
+  const int nblk = (g.n_freq + cb - 1) / cb;
+#define TFFR_RMA_POS_CB(CBV)                                                                         \
+  if (cb == CBV) {                                                                                 \
+    constexpr int NT = nt_cols<L, CBV>();                                                          \
+    auto fn = k_rma_front_pos<R, L, NT, CBV>;                                                      \
+    hipError_t e = allow_lds((const void*)fn, lds);                                                \
+    if (e != hipSuccess) return e;                                                                 \
+    hipLaunchKernelGGL(fn, dim3(nblk), dim3(NT), lds, st, g, t, echoes, pos, J, S, xc, stype, out); \
+    return hipGetLastError();                                                                      \
+  }
+  TFFR_LOGN_DISPATCH(logg, {
+    TFFR_RMA_POS_CB(16)
+    TFFR_RMA_POS_CB(8)
+    TFFR_RMA_POS_CB(4)
+    TFFR_RMA_POS_CB(2)
+    TFFR_RMA_POS_CB(1)
+    return hipErrorInvalidValue;
+  })
+#undef TFFR_RMA_POS_CB
+}
+
+template <typename R>
 hipError_t launch_stolt_rows(const Geo& g, const Tab<R>& t, int stype, const void* samples, const R* phase,
                              const R* dalong, int part, cplx<R>* out, hipStream_t st) {
   const size_t lds = sizeof(cplx<R>) * (((size_t)1 << g.lognfx) + ((size_t)1 << g.lognfx) / 64 + 64);
@@ -178,7 +275,9 @@ hipError_t launch_stolt_rows(const Geo& g, const Tab<R>& t, int stype, const voi
   template hipError_t launch_rma_front<R>(const Geo&, const Tab<R>&, int, const cplx<R>*, double, int, void*,    \
                                           hipStream_t);                                                          \
   template hipError_t launch_stolt_rows<R>(const Geo&, const Tab<R>&, int, const void*, const R*, const R*, int, \
-                                           cplx<R>*, hipStream_t);
+                                           cplx<R>*, hipStream_t);                                             \
+  template hipError_t launch_rma_front_pos<R>(const Geo&, const Tab<R>&, int, const cplx<R>*, const double*, int, \
+                                              int, double, int, void*, hipStream_t);
 
 TFFR_INSTANTIATE_TYPES
 

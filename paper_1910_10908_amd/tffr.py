@@ -149,8 +149,10 @@ class Plan:
                                          _ptr(out), _ptr(self.work), _stream()), "tffr_forward")
         return out
 
-    def tffr_rma_front_end(self, echoes, du, xc, out=None):
-        """Raw echoes [n_positions][n_freq] (complex compute type) -> samples of this plan."""
+    def tffr_rma_front_end(self, echoes, du, xc, out=None, dpos=None):
+        """Raw echoes [n_positions][n_freq] (complex compute type) -> samples of this plan.
+        dpos: host sequence of per-position along-track errors (m), or None for the
+        nominal positions."""
         J = int(echoes.shape[0]) if echoes.dim() >= 1 else 0
         ct = torch.complex128 if self.params.dtype == C128 else torch.complex64
         self._chk(echoes, (J, self.params.n_freq), ct, "echoes")
@@ -160,8 +162,16 @@ class Plan:
             else:
                 out = torch.empty(self.shape_samples, dtype=self.ctype, device=self.device)
         self._chk_samples(out)
-        _lib.check(self.lib.tffr_rma_front_end(self.handle, _ptr(echoes), J, float(du), float(xc), _ptr(out),
-                                               _stream()), "tffr_rma_front_end")
+        if dpos is None:
+            _lib.check(self.lib.tffr_rma_front_end(self.handle, _ptr(echoes), J, float(du), float(xc), _ptr(out),
+                                                   _stream()), "tffr_rma_front_end")
+            return out
+        d = np.ascontiguousarray(np.asarray(dpos, dtype=np.float64))
+        if d.shape != (J,):
+            raise ValueError(f"dpos must have shape ({J},), got {d.shape}")
+        _lib.check(self.lib.tffr_rma_front_end_pos(self.handle, _ptr(echoes), J, float(du),
+                                                   d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(xc),
+                                                   _ptr(out), _stream()), "tffr_rma_front_end_pos")
         return out
 
     def tffr_stolt_image(self, samples, phase=None, dalong=None, out=None):

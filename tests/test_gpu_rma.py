@@ -87,6 +87,77 @@ def test_front_end_rejects_mismatched_geometry():
     assert lib.tffr_rma_front_end(h, ptr(et), J, du, float("nan"), ptr(out), None) == 1
 
 
+@pytest.mark.parametrize("dtype", [T.C64, T.C128, T.C64_FP16IN])
+@pytest.mark.parametrize("n_pulses,n_freq,amp", [(64, 96, 0.4), (32, 200, 0.45), (64, 96, 0.0)])
+def test_front_end_position_errors_vs_oracle(dtype, n_pulses, n_freq, amp):
+    """Echoes recorded at u_j + d_j (d uniform within +-amp du): the non-uniform azimuth
+    transform against the oracle's sum at the true positions; amp 0 puts every source on
+    the nominal grid (the uniform front end's result, through the gridding path)."""
+    print(f"front end with position errors N_u {n_pulses} P {n_freq} amp {amp} dtype {dtype}", flush=True)
+    case, J, du = _front_case(n_pulses, n_freq, dtype)
+    d = np.random.default_rng(31 + n_pulses).uniform(-amp, amp, J) * du
+    e = _echoes(J, n_freq, 41 + n_pulses)
+    ct = torch.complex128 if dtype == T.C128 else torch.complex64
+    et = torch.as_tensor(e, dtype=ct, device=DEV)
+    got = _got(case.plan, case.plan.tffr_rma_front_end(et, du, 523.7, dpos=d))
+    ref, _ = ORMA.front_end(et.cpu().numpy().astype(np.complex128), case.k, du, 523.7, n_pulses, dpos=d)
+    e_max, e_l2 = _max_rel(got, ref), rel_l2(got, ref)
+    print(f"  max-rel {e_max:.2e} rel-L2 {e_l2:.2e}", flush=True)
+    tol = {T.C64: 1e-5, T.C128: 1e-10, T.C64_FP16IN: 1e-3}[dtype]
+    assert e_max < tol
+
+
+def test_front_end_position_errors_tone():
+    """A tone exp(+i ku_m u) recorded at the true positions transforms to J at bin m."""
+    n_pulses, n_freq = 64, 8
+    case, J, du = _front_case(n_pulses, n_freq, T.C64)
+    d = np.random.default_rng(5).uniform(-0.4, 0.4, J) * du
+    m = 60
+    u = (np.arange(J) - J / 2.0) * du + d
+    e = np.repeat(np.exp(1j * case.ku[m] * u)[:, None], n_freq, axis=1)
+    got = case.plan.tffr_rma_front_end(torch.as_tensor(e, dtype=torch.complex64, device=DEV), du, 0.0,
+                                       dpos=d).cpu().numpy()
+    assert np.max(np.abs(got[m] - J)) < 1e-5 * J
+
+
+def test_front_end_position_errors_rejected():
+    case, J, du = _front_case(64, 96, T.C64)
+    et = torch.zeros((J, 96), dtype=torch.complex64, device=DEV)
+    d = np.zeros(J)
+    d[40] = -1.5 * du  # position 40 falls behind position 39
+    with pytest.raises(RuntimeError, match="NONMONOTONE"):
+        case.plan.tffr_rma_front_end(et, du, 0.0, dpos=d)
+    d[40] = float("nan")
+    with pytest.raises(RuntimeError, match="ERR_ARG"):
+        case.plan.tffr_rma_front_end(et, du, 0.0, dpos=d)
+    d = np.zeros(J)
+    d[-1] = J * du  # the last position wraps past the first
+    with pytest.raises(RuntimeError, match="NONMONOTONE"):
+        case.plan.tffr_rma_front_end(et, du, 0.0, dpos=d)
+    with pytest.raises(ValueError):
+        case.plan.tffr_rma_front_end(et, du, 0.0, dpos=np.zeros(J - 1))
+
+
+def test_front_end_position_errors_full_size_sampled_columns():
+    """4096 x 8192 geometry (J = 8192 positions, an 8192-cell grid), positions within
+    +-0.45 du of nominal, all N_u rows of 8 sampled fast-time columns against the oracle."""
+    n_pulses, n_freq = 4096, 8192
+    k, ku = scenes.radar_sampling(n_pulses, n_freq)
+    J, du = scenes.rma_positions(n_pulses)
+    prm = T.default_params(n_pulses=n_pulses, n_freq=n_freq, mx=4096, my=4096, fov_x=400.0, fov_y=400.0)
+    plan = T.Plan(prm, k, ku, DEV)
+    d = np.random.default_rng(77).uniform(-0.45, 0.45, J) * du
+    et = torch.randn((J, n_freq), dtype=torch.complex64, device=DEV, generator=torch.Generator(DEV).manual_seed(7))
+    got = plan.tffr_rma_front_end(et, du, 1500.0, dpos=d)
+    cols = np.sort(np.random.default_rng(78).choice(n_freq, 8, replace=False))
+    e = et[:, torch.as_tensor(cols, device=DEV)].cpu().numpy().astype(np.complex128)
+    ref, _ = ORMA.front_end(e, k[cols], du, 1500.0, n_pulses, dpos=d)
+    g = got[:, torch.as_tensor(cols, device=DEV)].cpu().numpy()
+    e_max = _max_rel(g, ref)
+    print(f"  8 columns max-rel {e_max:.2e}", flush=True)
+    assert e_max < 1e-5
+
+
 def test_front_end_full_size_sampled_columns():
     """4096 x 8192 geometry (J = 8192 positions, the largest single-column LDS tile), all
     N_u rows of 16 sampled fast-time columns against the oracle."""
