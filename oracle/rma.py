@@ -45,6 +45,26 @@ def azimuth_wavenumbers(n_pulses, n_positions, du):
     return (np.arange(n_pulses, dtype=np.float64) - n_pulses / 2.0) * (2.0 * np.pi / (n_positions * du))
 
 
+def range_fft(pulses, ref=None):
+    """Range FFT and matched filter of time-domain pulses (Sec. II-A: the data are taken to
+    the frequency domain and matched filtered).
+
+    pulses: [J, P] complex baseband samples of each pulse at the rate of the bandwidth (P
+    samples), ref: [P] reference spectrum of the matched filter (None: ones, for data that
+    are already dechirped).  Returns E[j, p] = ref[p] sum_t pulses[j, t] exp(-2 pi i (p - P/2)
+    t / P): the centred frequency bins, p <-> f_p = fc + (p - P/2) bw / P, the fast-time
+    samples the front end takes.
+    """
+    r = np.asarray(pulses, dtype=np.complex128)
+    P = r.shape[1]
+    m = np.arange(P, dtype=np.float64) - P // 2
+    t = np.arange(P, dtype=np.float64)
+    E = r @ np.exp(-2j * np.pi * np.outer(t, m) / P)
+    if ref is not None:
+        E = E * np.asarray(ref, dtype=np.complex128)[None, :]
+    return E
+
+
 def front_end(echoes, k, du, xc, n_pulses, dpos=None):
     """Azimuth transform of raw echoes and reference-function multiply (see module doc).
 

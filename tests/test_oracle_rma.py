@@ -74,6 +74,35 @@ def test_front_end_focuses_a_point_scatterer(method):
     assert not (abs(x - xt) <= px and abs(y - yt) <= py)
 
 
+def test_range_fft_is_the_centred_library_fft():
+    """The range FFT is numpy's forward FFT of each pulse read at the centred bins
+    (p - P/2) mod P, times the reference spectrum."""
+    rng = np.random.default_rng(31)
+    r = rng.standard_normal((5, 64)) + 1j * rng.standard_normal((5, 64))
+    ref = np.exp(1j * rng.uniform(0, 2 * np.pi, 64))
+    E = rma.range_fft(r, ref)
+    F = np.fft.fft(r, axis=1)
+    m = np.arange(64) - 32
+    np.testing.assert_allclose(E, F[:, m % 64] * ref, rtol=0, atol=1e-10 * np.abs(F).max())
+
+
+def test_range_fft_delay_and_matched_filter():
+    """Closed forms: a pulse delayed by t0 samples becomes exp(-2 pi i (p - P/2) t0 / P); a
+    phase-coded pulse whose spectrum is the code C times X comes out as X through the
+    reference conj(C) (|C| = 1), the matched filter."""
+    P, t0 = 128, 37
+    r = np.zeros((1, P), complex)
+    r[0, t0] = 1.0
+    m = np.arange(P) - P // 2
+    np.testing.assert_allclose(rma.range_fft(r)[0], np.exp(-2j * np.pi * m * t0 / P), rtol=0, atol=1e-12)
+    rng = np.random.default_rng(32)
+    X = rng.standard_normal((3, P)) + 1j * rng.standard_normal((3, P))
+    C = np.exp(1j * np.pi * (m / P) ** 2 * P / 4)  # a linear-FM (chirp) code, unit modulus
+    spec = C * X  # the coded pulse's centred spectrum
+    pulses = np.fft.ifft(np.roll(spec, -P // 2, axis=1), axis=1)  # back to time samples
+    np.testing.assert_allclose(rma.range_fft(pulses, np.conj(C)), X, rtol=0, atol=1e-10 * np.abs(X).max())
+
+
 def test_front_end_position_errors_tone():
     """Per-pulse position errors: an azimuth tone exp(+i ku_m u) recorded at the true
     positions u_j + d_j transforms to exactly J at bin m (every term of the sum is 1) when
