@@ -195,6 +195,20 @@ tffr_status tffr_forward(tffr_plan *plan, const void *d_samples, const void *d_p
 tffr_status tffr_rma_front_end(tffr_plan *plan, const void *d_echoes, int32_t n_positions, double du,
                                double xc, void *d_samples, tffr_stream stream);
 
+/* Range FFT and matched filter (Sec. II-A: the data are taken to the frequency domain and
+ * matched filtered before the azimuth transform):
+ *   d_pulses  [n_positions][n_freq] complex (complex128 for TFFR_C128, else complex64):
+ *             each pulse's n_freq baseband time samples at the rate of the bandwidth
+ *   d_ref     [n_freq] complex reference spectrum of the matched filter, or NULL (ones:
+ *             data already dechirped)
+ *   d_echoes  [n_positions][n_freq] complex, written (may alias d_pulses):
+ *             d_echoes[j][p] = ref[p] sum_t d_pulses[j][t] exp(-2 pi i (p - n_freq/2) t / n_freq),
+ *             the centred frequency bins, p <-> k_p ascending, as tffr_rma_front_end takes.
+ * n_freq must be a power of two, 64 ... 16384 (8192 for TFFR_C128), else
+ * TFFR_ERR_UNSUPPORTED; TFFR_ERR_ARG for NULL buffers or n_positions < 1; enqueue only. */
+tffr_status tffr_rma_range_fft(tffr_plan *plan, const void *d_pulses, int32_t n_positions, const void *d_ref,
+                               void *d_echoes, tffr_stream stream);
+
 /* The same front end for echoes recorded off their nominal positions (per-pulse
  * along-track position errors): echo j was recorded at u_j + dpos[j], and the azimuth sum
  *   d_samples[n][p] = exp(+i kx(n, p) xc) sum_j d_echoes[j][p] exp(-i ku_n (u_j + dpos[j]))

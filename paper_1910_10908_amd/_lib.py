@@ -65,6 +65,7 @@ _PROTOS = {
     "tffr_row_phase_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "tffr_coord_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tffr_rma_front_end": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _vp, _vp]),
+    "tffr_rma_range_fft": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp]),
     "tffr_rma_front_end_pos": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, ctypes.c_double,
                                               ctypes.POINTER(ctypes.c_double), ctypes.c_double, _vp, _vp]),
     "tffr_stolt_image": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),

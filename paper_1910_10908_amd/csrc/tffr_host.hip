@@ -979,6 +979,24 @@ tffr_status tffr_rma_front_end(tffr_plan* P, const void* echoes, int32_t n_posit
   return hip_status(e);
 }
 
+tffr_status tffr_rma_range_fft(tffr_plan* P, const void* pulses, int32_t n_positions, const void* ref, void* echoes,
+                               tffr_stream stream) {
+  if (!P || !pulses || !echoes || n_positions < 1) return TFFR_ERR_ARG;
+  const int Pf = P->prm.n_freq;
+  if ((Pf & (Pf - 1)) != 0 || Pf < 64 || Pf > 16384 || (P->dbl() && Pf > 8192)) return TFFR_ERR_UNSUPPORTED;
+  if (!aligned(pulses, P->csize() / 2) || !aligned(echoes, P->csize() / 2) || (ref && !aligned(ref, P->csize() / 2)))
+    return TFFR_ERR_LAYOUT;
+  int logp = 0;
+  while ((1 << logp) < Pf) ++logp;
+  hipStream_t st = (hipStream_t)stream;
+  const hipError_t e =
+      P->dbl() ? tffr::launch_rma_range_fft<double>(logp, n_positions, (const cplx<double>*)pulses,
+                                                    (const cplx<double>*)ref, (cplx<double>*)echoes, st)
+               : tffr::launch_rma_range_fft<float>(logp, n_positions, (const cplx<float>*)pulses,
+                                                   (const cplx<float>*)ref, (cplx<float>*)echoes, st);
+  return hip_status(e);
+}
+
 tffr_status tffr_rma_front_end_pos(tffr_plan* P, const void* echoes, int32_t n_positions, double du,
                                    const double* dpos, double xc, void* samples, tffr_stream stream) {
   if (!P || !echoes || !dpos || !samples) return TFFR_ERR_ARG;

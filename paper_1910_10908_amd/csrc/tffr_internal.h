@@ -128,6 +128,9 @@ template <typename R>
 hipError_t launch_rma_front(const Geo& g, const Tab<R>& t, int logj, const cplx<R>* echoes, double xc, int stype,
                             void* out, hipStream_t st);  // tffr_rma.hip
 template <typename R>
+hipError_t launch_rma_range_fft(int logp, int n_rows, const cplx<R>* pulses, const cplx<R>* ref, cplx<R>* echoes,
+                                hipStream_t st);
+template <typename R>
 hipError_t launch_rma_front_pos(const Geo& g, const Tab<R>& t, int logg, const cplx<R>* echoes, const double* pos,
                                 int J, int S, double xc, int stype, void* out, hipStream_t st);
 template <typename R>

@@ -1,4 +1,5 @@
-// Range-migration front end (uniform positions, and positions with per-pulse errors) and
+// Range-migration front end (range FFT and matched filter; azimuth transform at uniform
+// positions, or at positions with per-pulse errors) and
 // Stolt-interpolation baseline of libtffr (Sec. II-A; Sec. IV, Baselines).
 //
 // Front end: raw echoes e[j][p] at J along-track positions u_j = (j - J/2) du become the
@@ -68,6 +69,29 @@ __global__ __launch_bounds__(NT) void k_rma_front(Geo g, Tab<R> t, const cplx<R>
     } else {
       ((cplx<R>*)out)[o] = v;
     }
+  }
+}
+
+// Range FFT and matched filter: pulse j's P baseband time samples -> its centred frequency
+// bins E[j][p] = ref[p] sum_t r[j][t] exp(-2 pi i (p - P/2) t / P) (ref null: ones), the
+// fast-time samples the front end takes.  One pulse per workgroup, transformed in LDS; a
+// workgroup reads its whole row before writing it, so the output may alias the input.
+template <typename R, int LOGP, int NT>
+__global__ __launch_bounds__(NT) void k_rma_range_fft(const cplx<R>* pulses, const cplx<R>* __restrict__ ref,
+                                                      cplx<R>* echoes) {
+  constexpr int P = 1 << LOGP;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
+  cplx<R>* buf = tw + tw_entries<P>();
+  const size_t row = (size_t)blockIdx.x * P;
+  make_twiddles<P, NT>(tw);
+  for (int i = threadIdx.x; i < P; i += NT) buf[i] = pulses[row + i];
+  __syncthreads();
+  lds_fft<-1, P, NT, 1, 8, 1>(buf, tw);
+  for (int p = threadIdx.x; p < P; p += NT) {
+    cplx<R> v = buf[(p - P / 2) & (P - 1)];
+    if (ref) v = cmul(v, ref[p]);
+    echoes[row + p] = v;
   }
 }
 
@@ -221,6 +245,20 @@ hipError_t launch_rma_front(const Geo& g, const Tab<R>& t, int logj, const cplx<
 }
 
 template <typename R>
+hipError_t launch_rma_range_fft(int logp, int n_rows, const cplx<R>* pulses, const cplx<R>* ref, cplx<R>* echoes,
+                                hipStream_t st) {
+  const size_t lds = sizeof(cplx<R>) * (((size_t)1 << logp) + ((size_t)1 << logp) / 64 + 64);
+  TFFR_LOGN_DISPATCH(logp, {
+    constexpr int NT = nt_for<L>();
+    auto fn = k_rma_range_fft<R, L, NT>;
+    hipError_t e = allow_lds((const void*)fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fn, dim3(n_rows), dim3(NT), lds, st, pulses, ref, echoes);
+    return hipGetLastError();
+  })
+}
+
+template <typename R>
 hipError_t launch_rma_front_pos(const Geo& g, const Tab<R>& t, int logg, const cplx<R>* echoes, const double* pos,
                                 int J, int S, double xc, int stype, void* out, hipStream_t st) {
   const int G = 1 << logg;
@@ -276,6 +314,7 @@ hipError_t launch_stolt_rows(const Geo& g, const Tab<R>& t, int stype, const voi
                                           hipStream_t);                                                          \
   template hipError_t launch_stolt_rows<R>(const Geo&, const Tab<R>&, int, const void*, const R*, const R*, int, \
                                            cplx<R>*, hipStream_t);                                             \
+  template hipError_t launch_rma_range_fft<R>(int, int, const cplx<R>*, const cplx<R>*, cplx<R>*, hipStream_t);   \
   template hipError_t launch_rma_front_pos<R>(const Geo&, const Tab<R>&, int, const cplx<R>*, const double*, int, \
                                               int, double, int, void*, hipStream_t);
 

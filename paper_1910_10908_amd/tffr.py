@@ -149,6 +149,20 @@ class Plan:
                                          _ptr(out), _ptr(self.work), _stream()), "tffr_forward")
         return out
 
+    def tffr_rma_range_fft(self, pulses, ref=None, out=None):
+        """Time-domain pulses [n_positions][n_freq] -> their centred frequency bins times the
+        matched filter's reference spectrum ref [n_freq] (None: ones)."""
+        J = int(pulses.shape[0]) if pulses.dim() >= 1 else 0
+        ct = torch.complex128 if self.params.dtype == C128 else torch.complex64
+        self._chk(pulses, (J, self.params.n_freq), ct, "pulses")
+        self._chk(ref, (self.params.n_freq,), ct, "ref")
+        if out is None:
+            out = torch.empty_like(pulses)
+        self._chk(out, (J, self.params.n_freq), ct, "echoes")
+        _lib.check(self.lib.tffr_rma_range_fft(self.handle, _ptr(pulses), J, _ptr(ref), _ptr(out), _stream()),
+                   "tffr_rma_range_fft")
+        return out
+
     def tffr_rma_front_end(self, echoes, du, xc, out=None, dpos=None):
         """Raw echoes [n_positions][n_freq] (complex compute type) -> samples of this plan.
         dpos: host sequence of per-position along-track errors (m), or None for the

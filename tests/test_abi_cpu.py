@@ -153,6 +153,7 @@ def test_null_handles_are_rejected_without_device():
     assert lib.tffr_coord_grad(None, None, None, None, None, None, None, None, None, None) == 1
     assert lib.tffr_debug_plan_config(None, None, None, None) == 1
     assert lib.tffr_rma_front_end_pos(None, None, 64, 1.0, None, 0.0, None, None) == 1
+    assert lib.tffr_rma_range_fft(None, None, 1, None, None, None) == 1
     assert lib.tffr_debug_ent_cols(None, None, None, None, None, None) == 1
     assert lib.tffr_debug_ent_adj_rows(*([None] * 11)) == 1
     assert lib.tffr_debug_fft(3, 1, 1, 8, 0, None, None, None) == 1

@@ -87,6 +87,63 @@ def test_front_end_rejects_mismatched_geometry():
     assert lib.tffr_rma_front_end(h, ptr(et), J, du, float("nan"), ptr(out), None) == 1
 
 
+@pytest.mark.parametrize("dtype", [T.C64, T.C128])
+@pytest.mark.parametrize("with_ref", [False, True])
+@pytest.mark.parametrize("n_freq", [64, 256, 2048])
+def test_range_fft_vs_oracle(dtype, with_ref, n_freq):
+    """Range FFT and matched filter of random pulses against the oracle, in place."""
+    print(f"range FFT n_freq {n_freq} ref {with_ref} dtype {dtype}", flush=True)
+    case = Case(8, n_freq, 64, fov=40.0, dtype=dtype, width=7 if dtype != T.C128 else 14)
+    J = 24
+    ct = torch.complex128 if dtype == T.C128 else torch.complex64
+    r = _echoes(J, n_freq, 51 + n_freq)
+    rng = np.random.default_rng(52)
+    ref = np.exp(1j * rng.uniform(0, 2 * np.pi, n_freq)) * rng.uniform(0.5, 1.5, n_freq) if with_ref else None
+    rt = torch.as_tensor(r, dtype=ct, device=DEV)
+    rin = rt.cpu().numpy().astype(np.complex128)
+    reft = torch.as_tensor(ref, dtype=ct, device=DEV) if with_ref else None
+    got = case.plan.tffr_rma_range_fft(rt, reft, out=rt).cpu().numpy()  # in place
+    want = ORMA.range_fft(rin, reft.cpu().numpy().astype(np.complex128) if with_ref else None)
+    e = _max_rel(got, want)
+    print(f"  max-rel {e:.2e}", flush=True)
+    # FP64: rounding of log2(n_freq) Stockham stages with two-level twiddle products
+    assert e < (1e-6 if dtype == T.C64 else 1e-12)
+
+
+def test_range_fft_then_front_end_matches_frequency_echoes():
+    """Time-domain pulses of point scatterers (the frequency-domain echoes taken back to
+    time samples at the centred bins) through the range FFT and the front end give the
+    samples of the frequency-domain echoes; a unit reference and a chirp code with its
+    conjugate reference both recover them."""
+    n_pulses, n_freq = 64, 256
+    case, J, du = _front_case(n_pulses, n_freq, T.C64)
+    rng = np.random.default_rng(53)
+    x, y = rng.uniform(-10, 10, 5), rng.uniform(-0.2, 0.2, 5)
+    a = rng.standard_normal(5) + 1j * rng.standard_normal(5)
+    E = scenes.raw_echoes(case.k, J, du, 500.0, x, y, a)
+    m = np.arange(n_freq) - n_freq // 2
+    code = np.exp(1j * np.pi * (m / n_freq) ** 2 * n_freq / 4)
+    ref_s, _ = ORMA.front_end(E, case.k, du, 500.0, n_pulses)
+    for C in (np.ones(n_freq), code):
+        pulses = np.fft.ifft(np.roll(C * E, -n_freq // 2, axis=1), axis=1)
+        pt = torch.as_tensor(pulses, dtype=torch.complex64, device=DEV)
+        reft = torch.as_tensor(np.conj(C), dtype=torch.complex64, device=DEV)
+        echoes = case.plan.tffr_rma_range_fft(pt, reft)
+        got = case.plan.tffr_rma_front_end(echoes, du, 500.0).cpu().numpy()
+        e = rel_l2(got, ref_s)
+        print(f"  rel-L2 {e:.2e}", flush=True)
+        assert e < 1e-5
+
+
+def test_range_fft_rejects():
+    case = Case(8, 100, 64, fov=40.0)
+    r = torch.zeros((4, 100), dtype=torch.complex64, device=DEV)
+    with pytest.raises(RuntimeError, match="UNSUPPORTED"):
+        case.plan.tffr_rma_range_fft(r)
+    lib, h = case.plan.lib, case.plan.handle
+    assert lib.tffr_rma_range_fft(h, None, 4, None, None, None) == 1
+
+
 @pytest.mark.parametrize("dtype", [T.C64, T.C128, T.C64_FP16IN])
 @pytest.mark.parametrize("n_pulses,n_freq,amp", [(64, 96, 0.4), (32, 200, 0.45), (64, 96, 0.0)])
 def test_front_end_position_errors_vs_oracle(dtype, n_pulses, n_freq, amp):
