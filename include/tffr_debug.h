@@ -35,9 +35,11 @@ tffr_status tffr_debug_rows(tffr_plan *plan, int32_t stage, const void *d_sample
 tffr_status tffr_debug_cols(tffr_plan *plan, const void *d_hx, void *d_image, tffr_stream stream);
 
 /* Launch configuration the plan chose: range_mode 0 (sub-pass gridding: kernels wider
- * than 8 cells, literal lattice taps), 1 (runs of read-add-writes: every other plan) or 2
+ * than 8 cells, literal lattice taps), 1 (runs of read-add-writes: every other plan), 2
  * (the same runs two samples at a time: complex64, width 7, rows of 4096 cells and more,
- * samples under half a cell apart);
+ * samples under half a cell apart) or 3 (the same runs, two parts of a slice at once on
+ * twice the threads, each into its own LDS row: slices of several parts on rows of at
+ * most 4096 cells);
  * az_cols range columns per azimuth workgroup;
  * ent_fused 1 when tffr_entropy_step uses the fused azimuth kernel.  Any pointer may be
  * NULL. */

@@ -772,6 +772,27 @@ tffr_status plan_create(const tffr_params* p, const double* k, const double* ku,
   const HostKx hkx{k, ku, kx_tab, p->n_freq};
   range_schedule(p, hkx, nfx, lit ? 2 * (int)p->q : W, tffr::rows_threads(lognx), &g.sub, &g.part_len,
                  &g.range_mode, &g.run_pair);
+  {
+    // slices of several parts on rows of at most 4096 cells, where one workgroup per slice
+    // leaves fewer than four waves per SIMD: two parts at once, on twice the threads, each
+    // into its own LDS row (the rows are summed before the FFT).  That halves each lane's
+    // chain of dependent read-add-writes; on a full chip the idle half of an odd last part
+    // costs more than it saves.
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device) != hipSuccess || ncu < 1)
+      ncu = 256;
+    const int nparts = (p->n_freq + g.part_len - 1) / g.part_len;
+    const int nt = tffr::rows_threads(lognx);
+    const bool sparse_chip = (double)p->n_pulses * (nt / 64) < 4.0 * 4.0 * ncu;
+    g.run_parts = (g.range_mode == 1 && !g.run_pair && nparts >= 2 && lognx <= 12 && 2 * nt <= 1024 && sparse_chip)
+                      ? 2
+                      : 1;
+    if (const char* e = std::getenv("TFFR_RUN_PARTS")) {
+      const int v = std::atoi(e);
+      if (v == 1) g.run_parts = 1;
+      if (v == 2 && g.range_mode == 1 && !g.run_pair && lognx <= 12 && 2 * nt <= 1024) g.run_parts = 2;
+    }
+  }
   std::vector<double> dx = deapod_table(p->mx, nfx, W, P->beta), dy = deapod_table(p->my, nfy, W, P->beta);
   // front end with position errors: a grid of at least twice the azimuth bins
   P->logfg = 6;
@@ -1286,7 +1307,11 @@ tffr_status tffr_debug_ffr_route(const tffr_plan* P, int32_t* route, int32_t* la
 
 tffr_status tffr_debug_plan_config(const tffr_plan* P, int32_t* range_mode, int32_t* az_cols, int32_t* ent_fused) {
   if (!P) return TFFR_ERR_ARG;
-  if (range_mode) *range_mode = P->geo.range_mode == 1 && P->geo.run_pair ? 2 : P->geo.range_mode;
+  if (range_mode) {
+    *range_mode = P->geo.range_mode;
+    if (P->geo.range_mode == 1 && P->geo.run_pair) *range_mode = 2;
+    else if (P->geo.range_mode == 1 && P->geo.run_parts == 2) *range_mode = 3;
+  }
   if (az_cols) *az_cols = P->cb;
   if (ent_fused) *ent_fused = P->ent_fused ? 1 : 0;
   return TFFR_OK;

@@ -32,6 +32,7 @@ struct Geo {
   int32_t yemax;                // azimuth gridding: most (slice, tap) pairs reaching one cell
   int32_t keep0;                // threshold decision for a sample exactly on the lattice
   int32_t run_pair;             // run range kernel takes its samples two at a time (samples < 1/2 cell apart)
+  int32_t run_parts;            // run range kernel: parts gridded at once, one LDS row each (1 or 2)
   double beta;                  // ES kernel shape
   double tx_scale;              // kx -> cycles per range pixel: fov_x / (2 pi mx)
   double fov_x;                 // kx -> lattice coordinate: kx * fov_x / (2 pi)

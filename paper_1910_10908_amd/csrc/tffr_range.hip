@@ -181,7 +181,7 @@ constexpr int run_waves() {
   }
 }
 
-template <typename R, int LOGN, int NT, int WM, bool PAIR>
+template <typename R, int LOGN, int NT, int WM, bool PAIR, int QP>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(run_waves<R, LOGN, NT, PAIR>())))
 void k_fwd_rows_run(Geo g, Tab<R> t, int stype, const void* __restrict__ samples,
                                                      const R* __restrict__ phase, const R* __restrict__ dalong,
@@ -191,10 +191,13 @@ void k_fwd_rows_run(Geo g, Tab<R> t, int stype, const void* __restrict__ samples
   constexpr int DPT = (N + NT - 1) / NT;
   constexpr int NW = NT / 64;
   constexpr int PAD = 2 * WM;
+  constexpr int LPP = NT / QP;  // lanes per part in flight
+  static_assert(QP == 1 || (QP == 2 && LPP % 64 == 0), "parts in flight");
+  static_assert(NW <= kRunHaloInts, "one halo start per wave");
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem);
-  cplx<R>* buf = tw + tw_entries<N>();  // [N + PAD]
-  cplx<R>* halo = buf + N + PAD;        // [NW][PAD]
+  cplx<R>* buf = tw + tw_entries<N>();  // [QP][N + PAD]: one row per part in flight
+  cplx<R>* halo = buf + QP * (N + PAD);  // [NW][PAD]
   int* hcf = reinterpret_cast<int*>(halo + NW * PAD);  // [NW] halo's first cell (-1: none)
   float* lpoly = reinterpret_cast<float*>(hcf + kRunHaloInts);
   const int n = blockIdx.x;
@@ -204,14 +207,20 @@ void k_fwd_rows_run(Geo g, Tab<R> t, int stype, const void* __restrict__ samples
   const size_t base_s = (size_t)n * g.n_freq;
   load_twiddles<N, NT>(tw, t.twx);
   const float* poly = load_poly<NT>(g, t.poly, lpoly);
-  for (int i = threadIdx.x; i < N + PAD + NW * PAD; i += NT) buf[i] = {0, 0};
+  for (int i = threadIdx.x; i < QP * (N + PAD) + NW * PAD; i += NT) buf[i] = {0, 0};
+  // with QP = 2 the first half of the threads takes one part and the second half the next
+  // one, each in its own row (a slice's parts overlap once wrapped onto the row)
+  const int q = QP == 1 ? 0 : (int)threadIdx.x / LPP;
+  const int tq = (int)threadIdx.x - q * LPP;
+  cplx<R>* row = buf + q * (N + PAD);
   const cplx<R> rot = row_rotation(t, phase, dalong, n);
   const double ku = t.ku[n];
   const R halfw = (R)(0.5 * g.W), inv_halfw = (R)(2.0 / g.W), beta = es_shape<R>(g);
   __syncthreads();  // row zeroed, tables in LDS
-  for (int pa = 0; pa < g.n_freq; pa += plen) {
+  for (int pg = 0; pg < g.n_freq; pg += QP * plen) {
+    const int pa = pg + q * plen;
     const int pb = min(pa + plen, g.n_freq);
-    const int p0 = pa + S * (int)threadIdx.x;
+    const int p0 = pa + S * tq;
     const int p1 = min(p0 + S, pb);
     int cfirst = 0;
     // one sample's weighted value, first tap cell (unwrapped: only differences and the low
@@ -230,7 +239,7 @@ void k_fwd_rows_run(Geo g, Tab<R> t, int stype, const void* __restrict__ samples
     };
     auto single = [&](int c0, int k0, R f, cplx<R> c) {
       const int rel = c0 - cfirst;
-      cplx<R>* dst = (lane == 0 && rel < W) ? halo + wv * PAD + rel : buf + (c0 & (N - 1));
+      cplx<R>* dst = (lane == 0 && rel < W) ? halo + wv * PAD + rel : row + (c0 & (N - 1));
       const R z0 = ((R)k0 - f) * inv_halfw;
       switch (W) {  // uniform: one unrolled tap block per kernel width
 #define TFFR_RUN_TAPS(WW) \
@@ -301,7 +310,7 @@ void k_fwd_rows_run(Geo g, Tab<R> t, int stype, const void* __restrict__ samples
         if (W == 7 && has_b && (d == 0 || d == 1) && (kept_a || kept_b)) {
           // removed samples carry a zero value here
           const int rel = c0a - cfirst;
-          cplx<R>* dst = (lane == 0 && rel < W) ? halo + wv * PAD + rel : buf + (c0a & (N - 1));
+          cplx<R>* dst = (lane == 0 && rel < W) ? halo + wv * PAD + rel : row + (c0a & (N - 1));
           run_taps_pair<7>(dst, ((R)k0a - fa) * inv_halfw, ((R)k0b - fb) * inv_halfw, d == 1, inv_halfw, beta,
                            kept_a ? ca : cplx<R>{0, 0}, kept_b ? cb : cplx<R>{0, 0});
         } else {
@@ -310,7 +319,7 @@ void k_fwd_rows_run(Geo g, Tab<R> t, int stype, const void* __restrict__ samples
         }
       }
     }
-    if (lane == 0) hcf[wv] = p0 < p1 ? (cfirst & (N - 1)) : -1;
+    if (lane == 0) hcf[wv] = p0 < p1 ? q * (N + PAD) + (cfirst & (N - 1)) : -1;
     __syncthreads();
     // halos onto the row: distinct waves' halos hold distinct cells of the part
     for (int i = threadIdx.x; i < NW * PAD; i += NT) {
@@ -322,6 +331,10 @@ void k_fwd_rows_run(Geo g, Tab<R> t, int stype, const void* __restrict__ samples
       }
       halo[i] = cplx<R>{0, 0};
     }
+    __syncthreads();
+  }
+  if constexpr (QP == 2) {  // the second row onto the first
+    for (int i = threadIdx.x; i < N + PAD; i += NT) buf[i] = buf[i] + buf[N + PAD + i];
     __syncthreads();
   }
   // the pad onto the row start
@@ -506,11 +519,14 @@ __global__ __launch_bounds__(NT) void k_adj_rows(Geo g, Tab<R> t, int stype, con
 // the run kernel, paired (complex64 rows of 4096 cells and more, the plan's choice for
 // samples under half a cell apart) or one sample at a time
 template <typename R, int L, int NT>
-static auto run_kernel(bool pair) {
+static auto run_kernel(bool pair, bool two_parts) {
   if constexpr (sizeof(R) == 4 && L >= 12) {
-    if (pair) return k_fwd_rows_run<R, L, NT, kRunWindow, true>;
+    if (pair) return k_fwd_rows_run<R, L, NT, kRunWindow, true, 1>;
   }
-  return k_fwd_rows_run<R, L, NT, kRunWindow, false>;
+  if constexpr (L <= 12 && 2 * NT <= 1024 && 2 * NT / 64 <= kRunHaloInts) {
+    if (two_parts) return k_fwd_rows_run<R, L, 2 * NT, kRunWindow, false, 2>;
+  }
+  return k_fwd_rows_run<R, L, NT, kRunWindow, false, 1>;
 }
 
 #ifdef TFFR_EMIT_SHARED
@@ -539,15 +555,22 @@ hipError_t launch_fwd_rows(const Geo& g, const Tab<R>& t, int stype, const void*
   TFFR_LOGN_DISPATCH(g.lognfx, {
     constexpr int NT = nt_for<L>();
     static_assert(NT / 64 <= kRunHaloInts, "run kernel halos");
-    // run kernel: the row's pad and one halo per wave, 2 kRunWindow cells each
-    if (g.range_mode == 1) lds += sizeof(cplx<R>) * (size_t)(2 * kRunWindow) * (1 + NT / 64) + sizeof(int) * kRunHaloInts;
+    // run kernel: the row's pad and one halo per wave, 2 kRunWindow cells each; with two
+    // parts at once a second row with its pad, on twice the threads
+    constexpr bool can_two = L <= 12 && 2 * NT <= 1024 && 2 * NT / 64 <= kRunHaloInts;
+    const bool two = can_two && g.range_mode == 1 && g.run_parts == 2 && !g.run_pair;
+    const int nt = two ? 2 * NT : NT;
+    if (g.range_mode == 1) {
+      lds += sizeof(cplx<R>) * (size_t)(2 * kRunWindow) * (1 + nt / 64) + sizeof(int) * kRunHaloInts;
+      if (two) lds += sizeof(cplx<R>) * (((size_t)1 << L) + 2 * kRunWindow);
+    }
     auto fn = g.range_mode == 1
-                  ? run_kernel<R, L, NT>(g.run_pair != 0)
+                  ? run_kernel<R, L, NT>(g.run_pair != 0, two)
                   : (g.sub <= 4 ? k_fwd_rows<R, L, NT, 4>
                                 : (g.sub <= 8 ? k_fwd_rows<R, L, NT, 8> : k_fwd_rows<R, L, NT, 16>));
     hipError_t e = allow_lds((const void*)fn, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fn, dim3(g.n_pulses), dim3(NT), lds, st, g, t, stype, samples, phase, dalong, w, out, stage);
+    hipLaunchKernelGGL(fn, dim3(g.n_pulses), dim3(nt), lds, st, g, t, stype, samples, phase, dalong, w, out, stage);
     return hipGetLastError();
   })
 }

@@ -148,7 +148,7 @@ def test_entropy_step_bench_workload_vs_oracle(monkeypatch):
     per azimuth workgroup) and with one and four, against the oracle's image, entropy and
     gradients on every sample and every pulse."""
     wl, plan, prob = _workload_case("ffr_vs_tffr_c64")
-    assert plan.az_cols == 2 and plan.range_mode == 1 and plan.ent_fused
+    assert plan.az_cols == 2 and plan.range_mode == 3 and plan.ent_fused
     s = scenes.random_samples(wl.n_pulses, wl.n_freq, 901)
     rng = np.random.default_rng(902)
     phase = rng.normal(0, 0.5, wl.n_pulses)

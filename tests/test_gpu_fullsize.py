@@ -111,9 +111,10 @@ def test_precision_study_fp32_and_fp16_2k():
 def test_launch_configuration_by_density():
     """Sparse slices (512 x 1024: ~3.1-3.6 fine cells apart) and dense ones (2048 x 4096:
     0.8-0.9 cells apart) take the run range kernel at width 7, the densest (4096 x 8192:
-    under half a cell apart) its paired form; the literal lattice taps take the sub-pass
-    kernel; every full-size plan runs the fused entropy azimuth kernel."""
-    for name, mode in (("ffr_vs_tffr_c64", 1), ("autofocus_1k", 1), ("precision_2k", 1), ("full_swath_4k", 2)):
+    under half a cell apart) its paired form; 512 slices of two parts each (two waves per
+    SIMD with one workgroup per slice) grid both parts at once; the literal lattice taps
+    take the sub-pass kernel; every full-size plan runs the fused entropy azimuth kernel."""
+    for name, mode in (("ffr_vs_tffr_c64", 3), ("autofocus_1k", 1), ("precision_2k", 1), ("full_swath_4k", 2)):
         wl = scenes.WORKLOADS[name]
         k, ku = scenes.radar_sampling(wl.n_pulses, wl.n_freq)
         prm = T.default_params(n_pulses=wl.n_pulses, n_freq=wl.n_freq, mx=wl.m, my=wl.m, fov_x=wl.fov,

@@ -92,17 +92,25 @@ def test_range_gridding_modes_dense(size, mode, monkeypatch):
 
 # The run kernel at rows long enough for several waves of runs (NT = 256 on 2048- and
 # 4096-cell rows: the first run of each wave goes through its halo) and for several parts
-# (span beyond the row), dense and sparse, in both precisions; on 4096-cell complex64 rows
-# with samples under half a cell apart, its paired form (range mode 2).
+# (span beyond the row), dense and sparse, in both precisions, one part at a time and two
+# at once (range mode 3, twice the threads, one LDS row per part; an odd last part leaves
+# half the threads idle); on 4096-cell complex64 rows with samples under half a cell
+# apart, its paired form (range mode 2).
 @pytest.mark.parametrize("n_freq,fov,mx,dtype,mode", [
     (4000, 200.0, 1024, T.C64, 1), (6000, 300.0, 1024, T.C64, 1), (600, 200.0, 1024, T.C64, 1),
     (4000, 200.0, 1024, T.C128, 1), (6000, 300.0, 1024, T.C128, 1),
     (6600, 300.0, 2048, T.C64, 2), (13000, 600.0, 2048, T.C64, 2), (13000, 600.0, 2048, T.C128, 1)])
-def test_range_gridding_run_kernel_many_waves(n_freq, fov, mx, dtype, mode, monkeypatch):
-    print(f"gridding stage, run kernel n_freq={n_freq} fov={fov} mx={mx} dtype={dtype}", flush=True)
+@pytest.mark.parametrize("parts", ["1", "2"])
+def test_range_gridding_run_kernel_many_waves(n_freq, fov, mx, dtype, mode, parts, monkeypatch):
+    print(f"gridding stage, run kernel n_freq={n_freq} fov={fov} mx={mx} dtype={dtype} parts={parts}",
+          flush=True)
     monkeypatch.setenv("TFFR_RANGE_MODE", "1")
+    monkeypatch.setenv("TFFR_RUN_PARTS", parts)
     case = Case(2, n_freq, mx, fov=fov, weighting=T.W_TFFR, dtype=dtype, seed=17)
-    assert case.plan.range_mode == mode and case.plan.nfine[0] == 2 * mx
+    print(f"  range mode {case.plan.range_mode}", flush=True)
+    # two parts at once (mode 3) on rows of at most 4096 cells, never with pairs
+    assert case.plan.range_mode == (3 if parts == "2" and mode == 1 else mode)
+    assert case.plan.nfine[0] == 2 * mx
     s, st = case.samples()
     phase = case.rng.normal(0, 0.5, 2)
     got = case.plan.tffr_debug_rows(st, stage=0, phase=case.real(phase)).cpu().numpy()
