@@ -72,14 +72,27 @@ __global__ __launch_bounds__(NT) void k_fwd_cols(Geo g, Tab<R> t, const cplx<R>*
 }
 
 // Image entropy from the per-block sums: E = ln S - (1/S) sum a ln a.  One block.
-// stats[0] = S, stats[1] = E; *loss = E.
+// stats[0] = S, stats[1] = E; *loss = E.  Each thread issues its (S, T) pair loads four
+// at a time (one 16-byte load per pair), so the whole reduction waits on one or two
+// memory latencies rather than one per pair.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_entropy_stats(const double* __restrict__ partials, int nparts,
                                                       double* __restrict__ stats, double* __restrict__ loss) {
+  constexpr int U = 4;
+  const double2* pp = reinterpret_cast<const double2*>(partials);
   double s = 0.0, tl = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += NT) {
-    s += partials[2 * i];
-    tl += partials[2 * i + 1];
+  for (int i0 = threadIdx.x; i0 < nparts; i0 += U * NT) {
+    double2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * NT;
+      v[u] = i < nparts ? pp[i] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      s += v[u].x;
+      tl += v[u].y;
+    }
   }
   s = block_sum<NT>(s);
   tl = block_sum<NT>(tl);
@@ -189,7 +202,7 @@ hipError_t launch_adj_cols(const Geo& g, const Tab<R>& t, int cb, const cplx<R>*
 
 #ifdef TFFR_EMIT_SHARED
 hipError_t launch_entropy_stats(const double* partials, int nparts, double* stats, double* loss, hipStream_t st) {
-  hipLaunchKernelGGL((k_entropy_stats<256>), dim3(1), dim3(256), 0, st, partials, nparts, stats, loss);
+  hipLaunchKernelGGL((k_entropy_stats<1024>), dim3(1), dim3(1024), 0, st, partials, nparts, stats, loss);
   return hipGetLastError();
 }
 #endif
