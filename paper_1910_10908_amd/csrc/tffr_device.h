@@ -260,19 +260,24 @@ __device__ __forceinline__ void fft_stage(cplx<R>* buf, const cplx<R>* tw) {
 
 constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 // Radix of the stage after spans P: MAXRAD while it fits, then what is left.  With
-// MAXRAD 8 and log2 N = 1 mod 3 (16, 128, 1024, 8192) the first stage takes radix 16,
-// so no radix-2 stage is left at the end (8192: 16 8 8 8 instead of 8 8 8 8 2).
-template <int N, int P, int MAXRAD>
+// MAXRAD 8, radix-16 first stages take the place of a small last stage: one where
+// log2 N = 1 mod 3 (16, 128, 1024, 8192: 16 8 8 8 instead of 8 8 8 8 2), and in single
+// precision two where log2 N = 2 mod 3 from 256 points up (2048: 16 16 8 instead of
+// 8 8 8 4; in double precision the second radix-16 stage's registers cost more).
+template <int N, int P, int MAXRAD, int RB>
 constexpr int stage_radix() {
-  if constexpr (MAXRAD == 8 && P == 1 && ilog2c(N) % 3 == 1 && ilog2c(N) >= 4) return 16;
+  constexpr int lg = ilog2c(N);
+  if constexpr (MAXRAD == 8 && P == 1 && lg % 3 == 1 && lg >= 4) return 16;
+  if constexpr (MAXRAD == 8 && RB == 4 && (P == 1 || P == 16) && lg % 3 == 2 && lg >= 8) return 16;
   return (N / P) >= MAXRAD ? MAXRAD : (N / P);
 }
 
 template <int SIGN, int N, int P, int NT, int NBAT, int MAXRAD, int SWZ, typename R>
 __device__ __forceinline__ void fft_from(cplx<R>* buf, const cplx<R>* tw) {
   if constexpr (P < N) {
-    constexpr int RAD = stage_radix<N, P, MAXRAD>();
-    constexpr bool in = P > 1 && (SWZ == 1 || (SWZ == 2 && P == stage_radix<N, 1, MAXRAD>()));
+    constexpr int RB = (int)sizeof(R);
+    constexpr int RAD = stage_radix<N, P, MAXRAD, RB>();
+    constexpr bool in = P > 1 && (SWZ == 1 || (SWZ == 2 && P == stage_radix<N, 1, MAXRAD, RB>()));
     constexpr bool out = P * RAD < N && (SWZ == 1 || (SWZ == 2 && P == 1));
     fft_stage<SIGN, N, RAD, P, NT, NBAT, in, out>(buf, tw);
     fft_from<SIGN, N, P * RAD, NT, NBAT, MAXRAD, SWZ>(buf, tw);
@@ -282,8 +287,8 @@ __device__ __forceinline__ void fft_from(cplx<R>* buf, const cplx<R>* tw) {
 // out[j] = sum_g buf[g] exp(SIGN 2 pi i g j / N) for NBAT transforms stored back to back
 // in LDS, in place, natural order; tw is the LDS twiddle table.  Call with all NT
 // threads after a barrier.
-// Stages of radix MAXRAD (8 or 16) and one smaller last stage (with MAXRAD 8, a radix-16
-// first stage where that removes a radix-2 last stage: see stage_radix).  Radix 16 takes fewer LDS
+// Stages of radix MAXRAD (8 or 16) and one smaller last stage (with MAXRAD 8, one or two
+// radix-16 first stages where that removes the small last stage: see stage_radix).  Radix 16 takes fewer LDS
 // passes and, in the dense-slice range kernel, fewer registers (more workgroups per CU);
 // radix 8 keeps more threads busy per stage where a workgroup has few butterflies.
 // SWZ: 0 plain layout; 1 every value between stages in the bank-spreading layout

@@ -351,8 +351,9 @@ void k_fwd_rows_run(Geo g, Tab<R> t, int stype, const void* __restrict__ samples
     const int jx = threadIdx.x + j * NT;
     dx[j] = jx < mx ? t.deapx[jx] : (R)0;
   }
-  // radix 16 (fewer LDS passes); 8192 points as 16 8 8 8 rather than 16 16 16 2
-  lds_fft<+1, N, NT, 1, (LOGN == 13 ? 8 : 16), 1>(buf, tw);
+  // radix 16 (fewer LDS passes); 8192 single-precision points as 16 8 8 8 rather than
+  // 16 16 16 2
+  lds_fft<+1, N, NT, 1, (LOGN == 13 && sizeof(R) == 4 ? 8 : 16), 1>(buf, tw);
 #pragma unroll
   for (int j = 0; j < DPT; ++j) {
     const int jx = threadIdx.x + j * NT;
