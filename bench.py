@@ -308,6 +308,8 @@ def pass_report(name, us, alg_bytes, wl_name):
     """Time, algorithmic bytes and every ceiling's fraction for one kernel of the step: HBM
     (algorithmic bytes, and counter-measured bytes where the counters are current), VALU
     busy and LDS busy (committed SQ counters); `binding` names the largest."""
+    from paper_1910_10908_amd import profiling
+
     t = us * 1e-6
     rec = {"us": us, "alg_bytes": alg_bytes, "achieved_GBps": alg_bytes / t / 1e9,
            "hbm_frac": alg_bytes / t / 1e9 / HBM_PEAK_GBS}
@@ -324,6 +326,11 @@ def pass_report(name, us, alg_bytes, wl_name):
         if key in sq:
             rec[key] = float(sq[key])
     rec["fractions"] = fr
+    # the committed rocprofv3 trace of the same workload, where taken on the current sources
+    tus, th = profiling.read_trace_avg(os.path.join(ROOT, "profiles", f"kernel_trace_{wl_name}.md"), name)
+    if tus is not None and th == profiling.kernel_source_hash():
+        rec["us_trace"] = tus
+        rec["us_over_trace"] = us / tus
     top = max(fr, key=fr.get)
     rec["binding"] = {"ceiling": "hbm" if top.startswith("hbm") else top, "frac": fr[top]}
     return rec
@@ -343,22 +350,27 @@ def alg_bytes_of(name, wl):
 
 
 def step_passes(T, plan, step, wl, fused, nsteps, step_us):
-    """Each launch of the step, timed with HIP events between the step's own launches (same
-    order, data flow and caches as the timed steps).  An event between two launches makes
-    the second wait for the first's completion to be recorded, which the plain step
-    overlaps with the next dispatch; the event times are therefore scaled by the plain
-    step's time over their sum ("us"; the raw event times are "us_events")."""
-    times = plan.tffr_debug_step_kernel_times(step.s, step.ph, step.da, None,
-                                              out=(step.img, step.loss, step.gs, step.gph, step.gda), nsteps=nsteps)
-    scale = min(1.0, step_us / sum(times.values()))
+    """Each launch of the step, in the step's own order, data flow and caches.
+    "us_events": the time between HIP events recorded between the step's launches.  Each
+    event makes the next launch wait for the previous one's completion to be recorded,
+    which adds about the same few microseconds to every launch, so "us" takes the excess
+    of their sum over the plain step (`step_us`, no events inside) off every launch in
+    equal shares.  "us_marginal": what one more launch adds to the step (plain steps
+    against steps that issue that launch twice, events around the loops only); the
+    repeated launch finds its inputs in cache, so on small steps it reads low."""
+    outs = (step.img, step.loss, step.gs, step.gph, step.gda)
+    times_ev = plan.tffr_debug_step_kernel_times(step.s, step.ph, step.da, None, out=outs, nsteps=nsteps)
+    times_mg = plan.tffr_debug_step_kernel_marginal_times(step.s, step.ph, step.da, None, out=outs, nsteps=nsteps)
+    share = max(0.0, sum(times_ev.values()) - step_us) / len(times_ev)
     out = {}
-    for name, us_ev in times.items():
-        us = us_ev * scale
+    for name, us_ev in times_ev.items():
+        us = max(us_ev - share, 0.5 * us_ev)
         b = alg_bytes_of(name, wl)
         if name == "k_adj_rows":  # samples in, sample gradient out, plus its spectra input
             b = 16 * wl.n_samples + (16 if fused else 8) * wl.n_pulses * wl.m
         out[name] = pass_report(name, us, b, wl.name) if b else {"us": us}
         out[name]["us_events"] = us_ev
+        out[name]["us_marginal"] = times_mg.get(name)
     return out
 
 
@@ -573,7 +585,8 @@ def main():
     ms = ms_graph if use_graph else ms_eager
 
     # every launch of the step, timed with HIP events between the step's own launches (same
-    # order, data flow and caches as the timed steps); the slowest is the roofline kernel
+    # order, data flow and caches as the timed steps), less an equal share of the events'
+    # own cost; the slowest is the roofline kernel
     log("per-launch times inside the step")
     passes = step_passes(T, plan, step, wl, plan.ent_fused, max(50, args.steps), ms_eager * 1e3)
     timed = {n: r for n, r in passes.items() if "alg_bytes" in r}
@@ -603,7 +616,8 @@ def main():
                      "unit": "GB/s", "frac": kr["hbm_frac"], "traffic": kr["traffic"], "kernel_us": kr["us"],
                      "alg_bytes": kr["alg_bytes"], "copy_GBps": copy_gbs,
                      "frac_of_copy": kr["achieved_GBps"] / copy_gbs, "binding": kr["binding"],
-                     "fractions": kr["fractions"]},
+                     "fractions": kr["fractions"], "kernel_us_trace": kr.get("us_trace"),
+                     "kernel_us_over_trace": kr.get("us_over_trace")},
         "passes": passes,
         "launch": {"range_mode": plan.range_mode, "az_cols": plan.az_cols, "entropy_fused": plan.ent_fused},
         "kept_count": kept,

@@ -93,6 +93,20 @@ tffr_status tffr_debug_step_kernel_times(tffr_plan *plan, const void *d_samples,
                                          tffr_stream stream, int32_t nsteps, float *ms_out, int32_t *nkern,
                                          const char **names);
 
+/* Marginal per-launch times of the entropy step, without events between its launches:
+ * times `nsteps` plain steps (HIP events on `stream` around the loop only), then, for each
+ * launch i of the step, `nsteps` steps in which launch i is issued twice back to back;
+ * ms_out[i] is the difference of the two per-step averages, i.e. what one more launch i
+ * adds to the step in its steady state.  Every launch of the step overwrites its outputs
+ * (none accumulates), so repeating one leaves them as in a plain step; one plain step
+ * runs last, and the outputs are those of one step when the call returns.  Arguments
+ * and outputs as for tffr_debug_step_kernel_times; the call synchronises `stream`. */
+tffr_status tffr_debug_step_kernel_marginal_times(tffr_plan *plan, const void *d_samples, const void *d_phase,
+                                                  const void *d_dalong, const void *d_user_w, void *d_image,
+                                                  double *d_loss, void *d_grad_samples, void *d_grad_phase,
+                                                  void *d_grad_dalong, void *d_work, tffr_stream stream,
+                                                  int32_t nsteps, float *ms_out, int32_t *nkern, const char **names);
+
 #ifdef __cplusplus
 }
 #endif

@@ -79,6 +79,9 @@ _PROTOS = {
     "tffr_debug_step_kernel_times": (ctypes.c_int, [_vp] * 12 + [ctypes.c_int32, ctypes.POINTER(ctypes.c_float),
                                                                 ctypes.POINTER(ctypes.c_int32),
                                                                 ctypes.POINTER(ctypes.c_char_p)]),
+    "tffr_debug_step_kernel_marginal_times": (ctypes.c_int, [_vp] * 12 + [ctypes.c_int32, ctypes.POINTER(ctypes.c_float),
+                                                                         ctypes.POINTER(ctypes.c_int32),
+                                                                         ctypes.POINTER(ctypes.c_char_p)]),
     "tffr_debug_ffr_route": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_int32)]),
     "tffr_debug_plan_config": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),

@@ -436,10 +436,13 @@ hipError_t launch_ent_adj_rows(tffr_plan* P, const void* smp, const void* ph, co
 
 // The step's launches in order; with `mark` non-null, mark(i) runs before launch i and
 // mark(nk) after the last (per-launch timing), and *nk receives the number of launches.
+// Launch number `dup` is issued twice (marginal timing; every launch of the step writes
+// its outputs without accumulating, so a repeat leaves them as one launch would).
 template <typename R>
 tffr_status do_entropy_step(tffr_plan* P, const void* smp, const void* ph, const void* da, const void* uw, void* img,
                             double* loss, void* gs, void* gph, void* gda, void* work, hipStream_t st,
-                            hipError_t (*mark)(void*, int) = nullptr, void* mark_ctx = nullptr, int* nk = nullptr) {
+                            hipError_t (*mark)(void*, int) = nullptr, void* mark_ctx = nullptr, int* nk = nullptr,
+                            int dup = -1) {
   const tffr::Tab<R> t = tables<R>(P);
   const R* w = (const R*)uw;
   if (!w && P->prm.weighting == TFFR_W_FFR) w = (const R*)P->ffr_d.p;
@@ -451,33 +454,38 @@ tffr_status do_entropy_step(tffr_plan* P, const void* smp, const void* ph, const
   cplx<R>* h12 = (cplx<R>*)(wb + P->off_h12);
   R* cblk = (R*)(wb + P->off_cblk);
   int k = 0;
-  auto step = [&](hipError_t e) -> hipError_t {
+  // launch number k of the step: mark, launch (twice if k == dup)
+  auto issue = [&](hipError_t e, auto&& launch) -> hipError_t {
     if (e == hipSuccess && mark) e = mark(mark_ctx, k);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess && k == dup) e = launch();
     ++k;
     return e;
   };
   // range stage; azimuth forward + entropy sums + adjoint azimuth transforms of the two
   // gradient fields in one kernel (written interleaved); range
   // adjoint combining the fields with the global entropy sums
-  hipError_t e = step(hipSuccess);
-  if (e == hipSuccess)
-    e = tffr::launch_fwd_rows<R>(P->geo, t, sample_type(P), smp, (const R*)ph, (const R*)da, w, hx, 1, st);
+  hipError_t e = issue(hipSuccess, [&] {
+    return tffr::launch_fwd_rows<R>(P->geo, t, sample_type(P), smp, (const R*)ph, (const R*)da, w, hx, 1, st);
+  });
   // few partial sums: every adjoint block reduces them itself (no separate launch)
   const bool fuse = nparts <= kFuseStatsMax;
+  auto stats_launch = [&] { return tffr::launch_entropy_stats(part, nparts, stats, loss, st); };
   if (!P->ent_fused) {  // image round trip: forward azimuth stage, then the adjoint one
-    if ((e = step(e)) == hipSuccess) e = tffr::launch_fwd_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, part, st);
-    if (!fuse && (e = step(e)) == hipSuccess) e = tffr::launch_entropy_stats(part, nparts, stats, loss, st);
-    if ((e = step(e)) == hipSuccess)
-      e = fuse ? tffr::launch_adj_cols<R>(P->geo, t, P->cb, (const cplx<R>*)img, hx, nullptr, part, nparts, loss, st)
-               : tffr::launch_adj_cols<R>(P->geo, t, P->cb, (const cplx<R>*)img, hx, stats, nullptr, 0, nullptr, st);
-    if ((e = step(e)) == hipSuccess)
-      e = tffr::launch_adj_rows<R>(P->geo, t, sample_type(P), hx, smp, (const R*)ph, (const R*)da, w, (cplx<R>*)gs,
-                                   (R*)gph, (R*)gda, tffr::EntComb<R>{}, st);
+    e = issue(e, [&] { return tffr::launch_fwd_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, part, st); });
+    if (!fuse) e = issue(e, stats_launch);
+    e = issue(e, [&] {
+      return fuse ? tffr::launch_adj_cols<R>(P->geo, t, P->cb, (const cplx<R>*)img, hx, nullptr, part, nparts, loss, st)
+                  : tffr::launch_adj_cols<R>(P->geo, t, P->cb, (const cplx<R>*)img, hx, stats, nullptr, 0, nullptr, st);
+    });
+    e = issue(e, [&] {
+      return tffr::launch_adj_rows<R>(P->geo, t, sample_type(P), hx, smp, (const R*)ph, (const R*)da, w,
+                                      (cplx<R>*)gs, (R*)gph, (R*)gda, tffr::EntComb<R>{}, st);
+    });
   } else {
-    if ((e = step(e)) == hipSuccess)
-      e = tffr::launch_ent_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, part, cblk, h12, st);
-    if (!fuse && (e = step(e)) == hipSuccess) e = tffr::launch_entropy_stats(part, nparts, stats, loss, st);
-    if ((e = step(e)) == hipSuccess) e = launch_ent_adj_rows<R>(P, smp, ph, da, w, loss, gs, gph, gda, work, st);
+    e = issue(e, [&] { return tffr::launch_ent_cols<R>(P->geo, t, P->cb, hx, (cplx<R>*)img, part, cblk, h12, st); });
+    if (!fuse) e = issue(e, stats_launch);
+    e = issue(e, [&] { return launch_ent_adj_rows<R>(P, smp, ph, da, w, loss, gs, gph, gda, work, st); });
   }
   if (e == hipSuccess && mark) e = mark(mark_ctx, k);
   if (nk) *nk = k;
@@ -1292,6 +1300,59 @@ tffr_status tffr_debug_step_kernel_times(tffr_plan* P, const void* smp, const vo
   if (s != TFFR_OK) return s;
   for (int i = 0; i < nk; ++i) ms_out[i] = (float)(acc[i] / nsteps);
   *nkern = nk;
+  if (names) step_kernel_names(P, names);
+  return TFFR_OK;
+}
+
+tffr_status tffr_debug_step_kernel_marginal_times(tffr_plan* P, const void* smp, const void* ph, const void* da,
+                                                  const void* uw, void* img, double* loss, void* gs, void* gph,
+                                                  void* gda, void* work, tffr_stream stream, int32_t nsteps,
+                                                  float* ms_out, int32_t* nkern, const char** names) {
+  if (!P || !smp || !img || !loss || !gs || !work || !ms_out || !nkern || nsteps < 1) return TFFR_ERR_ARG;
+  if (P->prm.weighting == TFFR_W_USER && !uw) return TFFR_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t ev[2];
+  if (hipEventCreate(&ev[0]) != hipSuccess) return TFFR_ERR_HIP;
+  if (hipEventCreate(&ev[1]) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return TFFR_ERR_HIP;
+  }
+  // nsteps steps with launch `dup` issued twice (dup = -1: the plain step), events only
+  // around the loop, after one untimed step of the same kind
+  int nk = 0;
+  auto loop_ms = [&](int dup, double* ms) -> tffr_status {
+    tffr_status s = TFFR_OK;
+    for (int it = -1; it < nsteps && s == TFFR_OK; ++it) {
+      if (it == 0 && hipEventRecord(ev[0], st) != hipSuccess) return TFFR_ERR_HIP;
+      s = P->dbl() ? do_entropy_step<double>(P, smp, ph, da, uw, img, loss, gs, gph, gda, work, st, nullptr, nullptr,
+                                             &nk, dup)
+                   : do_entropy_step<float>(P, smp, ph, da, uw, img, loss, gs, gph, gda, work, st, nullptr, nullptr,
+                                            &nk, dup);
+    }
+    if (s != TFFR_OK) return s;
+    float t = 0.0f;
+    if (hipEventRecord(ev[1], st) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+        hipEventElapsedTime(&t, ev[0], ev[1]) != hipSuccess)
+      return TFFR_ERR_HIP;
+    *ms = (double)t / nsteps;
+    return TFFR_OK;
+  };
+  double base = 0.0, with = 0.0;
+  tffr_status s = loop_ms(-1, &base);
+  const int n = nk;
+  for (int i = 0; i < n && s == TFFR_OK; ++i) {
+    s = loop_ms(i, &with);
+    if (s == TFFR_OK) ms_out[i] = (float)(with - base);
+  }
+  if (s == TFFR_OK) {  // one plain step: the outputs are those of one step
+    s = P->dbl() ? do_entropy_step<double>(P, smp, ph, da, uw, img, loss, gs, gph, gda, work, st)
+                 : do_entropy_step<float>(P, smp, ph, da, uw, img, loss, gs, gph, gda, work, st);
+    if (s == TFFR_OK && hipStreamSynchronize(st) != hipSuccess) s = TFFR_ERR_HIP;
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (s != TFFR_OK) return s;
+  *nkern = n;
   if (names) step_kernel_names(P, names);
   return TFFR_OK;
 }

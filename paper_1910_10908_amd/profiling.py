@@ -67,7 +67,23 @@ def trace_summary(path, only=None):
         if only and not any(o in n for o in only):
             continue
         lines.append(f"{n[:72]:72s} {c:6d} {a:10.3f} {t:12.1f}")
+    lines.append(f"source_hash: {kernel_source_hash()}")
     return "\n".join(lines)
+
+
+def read_trace_avg(path, kernel):
+    """Average traced duration (us) of `kernel` (name up to its template list) in a committed
+    kernel-trace summary, and the summary's kernel-source hash: (avg_us or None, hash or None)."""
+    avg, src = None, None
+    if not os.path.exists(path):
+        return avg, src
+    with open(path) as f:
+        for line in f:
+            if line.startswith("source_hash:"):
+                src = line.split(":", 1)[1].strip()
+            elif line.startswith(f"tffr::{kernel}<"):
+                avg = float(line[72:].split()[1])
+    return avg, src
 
 
 def _pmc_dispatches(path, counter):

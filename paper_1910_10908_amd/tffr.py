@@ -304,6 +304,21 @@ class Plan:
                                                          ctypes.byref(nk), names), "tffr_debug_step_kernel_times")
         return {names[i].decode(): ms[i] * 1e3 for i in range(nk.value)}
 
+    def tffr_debug_step_kernel_marginal_times(self, samples, phase=None, dalong=None, user_w=None, out=None,
+                                              nsteps=100):
+        """What one more launch of each kernel adds to the entropy step (plain steps against
+        steps with that launch issued twice; events around the loops only): {kernel name:
+        microseconds}, in the step's order."""
+        img, loss, gs, gph, gda = out
+        ms = (ctypes.c_float * 7)()
+        nk = ctypes.c_int32()
+        names = (ctypes.c_char_p * 7)()
+        _lib.check(self.lib.tffr_debug_step_kernel_marginal_times(
+            self.handle, _ptr(samples), _ptr(phase), _ptr(dalong), _ptr(user_w), _ptr(img), _ptr(loss), _ptr(gs),
+            _ptr(gph), _ptr(gda), _ptr(self.work), _stream(), nsteps, ms, ctypes.byref(nk), names),
+            "tffr_debug_step_kernel_marginal_times")
+        return {names[i].decode(): ms[i] * 1e3 for i in range(nk.value)}
+
     def tffr_weights(self, out=None):
         shape = self.shape_samples
         if self.params.weighting == W_FFR:

@@ -156,6 +156,8 @@ def test_null_handles_are_rejected_without_device():
     assert lib.tffr_rma_range_fft(None, None, 1, None, None, None) == 1
     assert lib.tffr_debug_ent_cols(None, None, None, None, None, None) == 1
     assert lib.tffr_debug_ent_adj_rows(*([None] * 11)) == 1
+    assert lib.tffr_debug_step_kernel_times(*([None] * 12), 10, None, None, None) == 1
+    assert lib.tffr_debug_step_kernel_marginal_times(*([None] * 12), 10, None, None, None) == 1
     assert lib.tffr_debug_fft(3, 1, 1, 8, 0, None, None, None) == 1
     out = ctypes.c_void_p()
     k, ku = scenes.radar_sampling(8, 16)

@@ -356,6 +356,25 @@ def test_entropy_step_matches_separate_calls_and_oracle(dtype, width):
     assert np.max(np.abs(gda.cpu().numpy() - rgda)) < tol * np.max(np.abs(rgda))
 
 
+def test_marginal_launch_timing_leaves_one_step_outputs():
+    """The marginal per-launch timing issues each launch of the step twice in turn; every
+    launch overwrites its outputs, so afterwards they equal one plain step's bit for bit,
+    and it reports the same launches, in order, as the event timing."""
+    print("marginal per-launch timing", flush=True)
+    case = Case(64, 128, 128, weighting=T.W_TFFR, seed=24)
+    s, st = case.samples()
+    ph = case.real(case.rng.normal(0, 0.5, 64))
+    da = case.real(case.rng.normal(0, 0.004, 64))
+    ref = [t.clone() for t in case.plan.tffr_entropy_step(st, ph, da)]
+    out = tuple(torch.full_like(t, 7.0) for t in ref)
+    marg = case.plan.tffr_debug_step_kernel_marginal_times(st, ph, da, out=out, nsteps=5)
+    ev = case.plan.tffr_debug_step_kernel_times(st, ph, da, out=tuple(torch.empty_like(t) for t in ref), nsteps=5)
+    print(f"  marginal {marg}  events {ev}", flush=True)
+    assert list(marg) == list(ev) and len(marg) >= 3
+    for a, b in zip(out, ref):
+        assert torch.equal(a, b)
+
+
 @pytest.mark.parametrize("weighting", [T.W_TFFR, T.W_FFR])
 def test_graph_replays_match_eager(weighting):
     """The fused step captured in a HIP graph gives the eager result on every replay,
